@@ -1,0 +1,594 @@
+/*
+ * CPU ORACLE for exact k-clique counting -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded and meant to be obviously correct.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * GPU library never does, and the two share no code.
+ *
+ * Paper: Almasri, El Hajj, Nagi, Xiong, Hwu, "Parallel K-clique Counting on GPUs"
+ * (ICS 2022, arXiv 2104.13209).
+ *
+ * What it computes
+ *   c_k(G) = number of k-vertex subsets of V that are pairwise adjacent (Sec. 1
+ *   problem statement), reached through the paper's two search-tree recursions:
+ *     - graph orientation (Sec. 2.2, Fig. 2), vertex-rooted or edge-rooted;
+ *     - pivoting (Sec. 2.3, Fig. 3) in the hybrid form of Sec. 2.3 / 2.4: the first
+ *       level (vertex root) or first two levels (edge root) follow the oriented
+ *       graph, every level below works on undirected adjacency.
+ *   All intersections are merges of sorted int vectors (or binary search when one
+ *   list is far shorter); there is no blocking, fusion or bit encoding here.
+ *
+ * Readings of the paper (each also listed in the design notes):
+ *   R1  In Fig. 3, l is the number of path vertices before the branch vertex v:
+ *       the vertex-rooted call starts at l = 1 (the root is a hold), the
+ *       edge-rooted call at l = 2.  Then l + 1 is the path length n_v and the
+ *       leaf term C(nPivots', l + 1 - k) equals Sec. 2.3's C(n_p, n_v - k).
+ *   R2  Pivot = argmax over u in I of |I intersect Adj(u)|; ties go to the
+ *       smallest vertex id.  (Any pivot in I gives the same count.)
+ *   R3  The order "<" in Fig. 3's exclusion set is vertex id order.
+ *   R4  Degree order: edge u->v iff (deg u, u) < (deg v, v).
+ *   R5  Degeneracy order: repeatedly remove a vertex of minimum current degree,
+ *       smallest id first on ties (Matula-Beck); edge u->v iff u is removed first.
+ *   R6  k = 1 gives n, k = 2 gives m (outside the pseudocode); counts[0] = 1 is
+ *       the empty clique.
+ *   R7  Counts are unsigned 128-bit; any carry out of bit 127 sets an overflow flag.
+ *
+ * Parity status: every function here is pinned by the CPU test suite against
+ * brute-force enumeration, closed forms, a library routine, or the paper's
+ * worked instance (see the tests); none is "parity unpinned".
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+enum { KCO_OK = 0, KCO_EINVAL = -1, KCO_ENOMEM = -2, KCO_EOVERFLOW = -3 };
+enum { KCO_DEGREE = 0, KCO_DEGENERACY = 1 };
+enum { KCO_VC = 1, KCO_EC = 2 };
+
+/* ------------------------------------------------------------------ input */
+
+/* 0 if (row_ptr, col) is a simple symmetric graph with strictly increasing rows
+ * and ids in range; KCO_EINVAL otherwise. */
+int kco_validate(int32_t n, const int32_t* row_ptr, const int32_t* col) {
+    if (n < 0 || row_ptr[0] != 0) return KCO_EINVAL;
+    for (int32_t v = 0; v < n; v++) {
+        if (row_ptr[v + 1] < row_ptr[v]) return KCO_EINVAL;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t w = col[e];
+            if (w < 0 || w >= n || w == v) return KCO_EINVAL;
+            if (e > row_ptr[v] && col[e - 1] >= w) return KCO_EINVAL;
+            /* symmetric: v must appear in w's row */
+            int32_t lo = row_ptr[w], hi = row_ptr[w + 1];
+            while (lo < hi) {
+                int32_t mid = lo + (hi - lo) / 2;
+                if (col[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            if (lo == row_ptr[w + 1] || col[lo] != v) return KCO_EINVAL;
+        }
+    }
+    return KCO_OK;
+}
+
+/* ------------------------------------------------------------ orientation */
+
+static const int32_t* g_deg_for_sort;
+static int cmp_degree_id(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    if (g_deg_for_sort[x] != g_deg_for_sort[y]) return g_deg_for_sort[x] < g_deg_for_sort[y] ? -1 : 1;
+    return (x > y) - (x < y);
+}
+
+/* Binary min-heap of (key, id) with lazy deletion, for the degeneracy peel. */
+typedef struct { int64_t* a; int64_t n, cap; } heap64;
+static int heap_push(heap64* h, int64_t x) {
+    if (h->n == h->cap) {
+        int64_t nc = h->cap ? 2 * h->cap : 1024;
+        int64_t* q = (int64_t*)realloc(h->a, (size_t)nc * sizeof(int64_t));
+        if (!q) return -1;
+        h->a = q; h->cap = nc;
+    }
+    int64_t i = h->n++;
+    h->a[i] = x;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h->a[p] <= h->a[i]) break;
+        int64_t t = h->a[p]; h->a[p] = h->a[i]; h->a[i] = t; i = p;
+    }
+    return 0;
+}
+static int64_t heap_pop(heap64* h) {
+    int64_t top = h->a[0];
+    h->a[0] = h->a[--h->n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, s = i;
+        if (l < h->n && h->a[l] < h->a[s]) s = l;
+        if (r < h->n && h->a[r] < h->a[s]) s = r;
+        if (s == i) break;
+        int64_t t = h->a[s]; h->a[s] = h->a[i]; h->a[i] = t; i = s;
+    }
+    return top;
+}
+
+/* Orientation (Sec. 3.1): rank[] is the position of each vertex in the order
+ * (R4 / R5); the DAG keeps edge u->v iff rank[u] < rank[v].  Out-lists are in
+ * vertex id order.  out_ptr has n+1 entries, out_col m = nnz/2 entries.
+ * *degeneracy receives the largest current degree seen at a removal (degeneracy
+ * order) or -1 (degree order). */
+int kco_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int order,
+               int32_t* out_ptr, int32_t* out_col, int32_t* rank,
+               int32_t* d_max, int32_t* degeneracy) {
+    if (n < 0 || (order != KCO_DEGREE && order != KCO_DEGENERACY)) return KCO_EINVAL;
+    int32_t* ids = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+    int32_t* deg = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+    if (!ids || !deg) { free(ids); free(deg); return KCO_ENOMEM; }
+    for (int32_t v = 0; v < n; v++) deg[v] = row_ptr[v + 1] - row_ptr[v];
+    *degeneracy = -1;
+    if (order == KCO_DEGREE) {
+        for (int32_t v = 0; v < n; v++) ids[v] = v;
+        g_deg_for_sort = deg;
+        qsort(ids, (size_t)n, sizeof(int32_t), cmp_degree_id);
+    } else {
+        /* Matula-Beck peel: pop the (current degree, id) minimum; skip stale
+         * heap entries; decrement the degrees of still-present neighbours. */
+        char* gone = (char*)calloc((size_t)(n ? n : 1), 1);
+        heap64 h = {0, 0, 0};
+        int32_t removed = 0, degen = 0;
+        if (!gone) { free(ids); free(deg); return KCO_ENOMEM; }
+        for (int32_t v = 0; v < n; v++)
+            if (heap_push(&h, ((int64_t)deg[v] << 32) | (uint32_t)v)) goto oom;
+        while (removed < n) {
+            int64_t x = heap_pop(&h);
+            int32_t v = (int32_t)(x & 0xffffffff), d = (int32_t)(x >> 32);
+            if (gone[v] || d != deg[v]) continue;       /* stale entry */
+            gone[v] = 1;
+            ids[removed++] = v;
+            if (d > degen) degen = d;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+                int32_t w = col[e];
+                if (!gone[w]) {
+                    deg[w]--;
+                    if (heap_push(&h, ((int64_t)deg[w] << 32) | (uint32_t)w)) goto oom;
+                }
+            }
+        }
+        *degeneracy = degen;
+        free(h.a); free(gone);
+        goto peeled;
+    oom:
+        free(h.a); free(gone); free(ids); free(deg);
+        return KCO_ENOMEM;
+    }
+peeled:
+    for (int32_t i = 0; i < n; i++) rank[ids[i]] = i;
+    int32_t dm = 0, pos = 0;
+    out_ptr[0] = 0;
+    for (int32_t u = 0; u < n; u++) {
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; e++)
+            if (rank[u] < rank[col[e]]) out_col[pos++] = col[e];
+        out_ptr[u + 1] = pos;
+        if (pos - out_ptr[u] > dm) dm = pos - out_ptr[u];
+    }
+    *d_max = dm;
+    free(ids); free(deg);
+    return KCO_OK;
+}
+
+/* ----------------------------------------------------------- set algebra */
+
+static int32_t find_ge(const int32_t* b, int32_t nb, int32_t x) {
+    int32_t lo = 0, hi = nb;
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (b[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* out = a intersect b (both sorted ascending); returns |out|. */
+static int32_t intersect(const int32_t* a, int32_t na, const int32_t* b, int32_t nb, int32_t* out) {
+    int32_t c = 0;
+    if ((int64_t)na * 16 < nb) {
+        for (int32_t i = 0; i < na; i++) {
+            int32_t j = find_ge(b, nb, a[i]);
+            if (j < nb && b[j] == a[i]) out[c++] = a[i];
+        }
+        return c;
+    }
+    if ((int64_t)nb * 16 < na) {
+        for (int32_t j = 0; j < nb; j++) {
+            int32_t i = find_ge(a, na, b[j]);
+            if (i < na && a[i] == b[j]) out[c++] = b[j];
+        }
+        return c;
+    }
+    int32_t i = 0, j = 0;
+    while (i < na && j < nb) {
+        if (a[i] < b[j]) i++;
+        else if (a[i] > b[j]) j++;
+        else { out[c++] = a[i]; i++; j++; }
+    }
+    return c;
+}
+
+static int contains(const int32_t* b, int32_t nb, int32_t x) {
+    int32_t j = find_ge(b, nb, x);
+    return j < nb && b[j] == x;
+}
+
+/* ------------------------------------------------------------ accumulation */
+
+typedef struct {
+    u128 total;
+    u128* counts;      /* count_all: counts[0..cap] */
+    int32_t cap;
+    u128* local;       /* local counts, per vertex (original ids) */
+    int overflow;
+    uint64_t nodes;    /* tree nodes visited (one per intersection with Adj(v)) */
+} acc_t;
+
+static void add128(u128* x, u128 y, int* ovf) {
+    u128 s = *x + y;
+    if (s < *x) *ovf = 1;
+    *x = s;
+}
+
+/* Pascal table C[i][j] for 0 <= j <= i <= N, with per-entry overflow marks. */
+typedef struct { int32_t N; u128* c; char* big; } binom_t;
+static int binom_init(binom_t* b, int32_t N) {
+    b->N = N;
+    b->c = (u128*)calloc((size_t)(N + 1) * (N + 1), sizeof(u128));
+    b->big = (char*)calloc((size_t)(N + 1) * (N + 1), 1);
+    if (!b->c || !b->big) return -1;
+    for (int32_t i = 0; i <= N; i++) {
+        b->c[(size_t)i * (N + 1)] = 1;
+        for (int32_t j = 1; j <= i; j++) {
+            u128 x = b->c[(size_t)(i - 1) * (N + 1) + j - 1];
+            u128 y = j <= i - 1 ? b->c[(size_t)(i - 1) * (N + 1) + j] : 0;
+            char big = b->big[(size_t)(i - 1) * (N + 1) + j - 1] |
+                       (j <= i - 1 ? b->big[(size_t)(i - 1) * (N + 1) + j] : 0);
+            u128 s = x + y;
+            if (s < x) big = 1;
+            b->c[(size_t)i * (N + 1) + j] = s;
+            b->big[(size_t)i * (N + 1) + j] = big;
+        }
+    }
+    return 0;
+}
+static void binom_free(binom_t* b) { free(b->c); free(b->big); }
+static u128 binom(const binom_t* b, int32_t i, int32_t j, int* ovf) {
+    if (j < 0 || j > i) return 0;
+    if (b->big[(size_t)i * (b->N + 1) + j]) *ovf = 1;
+    return b->c[(size_t)i * (b->N + 1) + j];
+}
+
+/* ---------------------------------------------------------------- graph */
+
+typedef struct {
+    int32_t n;
+    const int32_t *optr, *ocol;   /* oriented DAG, out-lists sorted by id */
+    const int32_t *uptr, *ucol;   /* undirected graph (pivoting levels) */
+    int32_t d_max;
+} graph_t;
+
+static const int32_t* outN(const graph_t* g, int32_t v, int32_t* len) {
+    *len = g->optr[v + 1] - g->optr[v];
+    return g->ocol + g->optr[v];
+}
+static const int32_t* undN(const graph_t* g, int32_t v, int32_t* len) {
+    *len = g->uptr[v + 1] - g->uptr[v];
+    return g->ucol + g->uptr[v];
+}
+
+/* Per-level vertex buffers (two of d_max + 1 entries each), allocated when a
+ * level is first reached. */
+typedef struct { int32_t** buf; int32_t nlev; int32_t width; int failed; } levels_t;
+static int32_t* level_buf(levels_t* L, int32_t l, int which) {
+    if (l >= L->nlev) {
+        int32_t nn = L->nlev ? L->nlev : 8;
+        while (nn <= l) nn *= 2;
+        int32_t** q = (int32_t**)realloc(L->buf, (size_t)nn * sizeof(int32_t*));
+        if (!q) { L->failed = 1; return NULL; }
+        for (int32_t i = L->nlev; i < nn; i++) q[i] = NULL;
+        L->buf = q; L->nlev = nn;
+    }
+    if (!L->buf[l]) {
+        L->buf[l] = (int32_t*)malloc((size_t)2 * L->width * sizeof(int32_t));
+        if (!L->buf[l]) { L->failed = 1; return NULL; }
+    }
+    return L->buf[l] + (size_t)which * L->width;
+}
+static void levels_free(levels_t* L) {
+    for (int32_t i = 0; i < L->nlev; i++) free(L->buf[i]);
+    free(L->buf);
+}
+
+/* Path of the current branch: `holds` gets the non-pivot vertices (all of them
+ * in graph orientation), `pivots` the pivots.  Grown on demand. */
+typedef struct { int32_t* v; int32_t cap; } path_t;
+static int path_set(path_t* p, int32_t i, int32_t x) {
+    if (i >= p->cap) {
+        int32_t nc = p->cap ? 2 * p->cap : 16;
+        while (nc <= i) nc *= 2;
+        int32_t* q = (int32_t*)realloc(p->v, (size_t)nc * sizeof(int32_t));
+        if (!q) return -1;
+        p->v = q; p->cap = nc;
+    }
+    p->v[i] = x;
+    return 0;
+}
+
+enum { MODE_K = 0, MODE_ALL = 1, MODE_LOCAL = 2 };
+
+typedef struct {
+    const graph_t* g;
+    int32_t k;
+    int mode;
+    const binom_t* bn;
+    levels_t lev;
+    path_t holds, pivots;
+    acc_t* acc;
+} ctx_t;
+
+/* ------------------------------------------- graph orientation (Fig. 2) */
+
+/* Fig. 2: the l path vertices are the current clique; I holds their common
+ * out-neighbours.  Each v in I extends the clique; the next level is
+ * I' = I cap Adj(v).  At l + 1 == k the |I'| k-cliques are counted and the branch
+ * stops.  (In count-all mode every level adds |I'| to counts[l + 1].) */
+static void go_rec(ctx_t* c, int32_t l, const int32_t* I, int32_t nI) {
+    int32_t* Ip = level_buf(&c->lev, l, 0);
+    if (!Ip) return;
+    for (int32_t i = 0; i < nI; i++) {
+        int32_t v = I[i], na;
+        const int32_t* a = outN(c->g, v, &na);
+        int32_t nIp = intersect(I, nI, a, na, Ip);
+        c->acc->nodes++;
+        if (path_set(&c->holds, l - 1, v)) { c->lev.failed = 1; return; }
+        if (c->mode == MODE_ALL) {
+            if (l + 1 <= c->acc->cap) add128(&c->acc->counts[l + 1], (u128)nIp, &c->acc->overflow);
+            if (nIp > 0) go_rec(c, l + 1, Ip, nIp);
+        } else if (l + 1 == c->k) {
+            if (c->mode == MODE_K) {
+                add128(&c->acc->total, (u128)nIp, &c->acc->overflow);
+            } else {
+                /* each of the l path vertices lies in all nIp k-cliques found
+                 * here; each vertex of I' in exactly one */
+                for (int32_t q = 0; q < l; q++)
+                    add128(&c->acc->local[c->holds.v[q]], (u128)nIp, &c->acc->overflow);
+                for (int32_t j = 0; j < nIp; j++)
+                    add128(&c->acc->local[Ip[j]], 1, &c->acc->overflow);
+            }
+        } else if (nIp > 0) {
+            go_rec(c, l + 1, Ip, nIp);
+        }
+        if (c->lev.failed) return;
+    }
+}
+
+/* ---------------------------------------------------- pivoting (Fig. 3) */
+
+/* A leaf with nh holds and np pivots stands for the cliques H u P' with P' any
+ * subset of the pivots (Sec. 2.3: C(n_p, n_v - k) k-cliques on a path of n_v
+ * vertices). */
+static void piv_leaf(ctx_t* c, int32_t nh, int32_t np) {
+    acc_t* a = c->acc;
+    int32_t k = c->k;
+    if (c->mode == MODE_K) {
+        if (nh + np >= k) add128(&a->total, binom(c->bn, np, nh + np - k, &a->overflow), &a->overflow);
+    } else if (c->mode == MODE_ALL) {
+        for (int32_t j = 0; j <= np; j++)
+            if (nh + j <= a->cap) add128(&a->counts[nh + j], binom(c->bn, np, j, &a->overflow), &a->overflow);
+    } else if (nh <= k && k - nh <= np) {
+        /* a hold is in every one of the C(np, k - nh) k-cliques, a pivot in those
+         * whose P' contains it: C(np - 1, k - nh - 1) */
+        u128 per_hold = binom(c->bn, np, k - nh, &a->overflow);
+        u128 per_pivot = binom(c->bn, np - 1, k - nh - 1, &a->overflow);
+        for (int32_t q = 0; q < nh; q++) add128(&a->local[c->holds.v[q]], per_hold, &a->overflow);
+        for (int32_t q = 0; q < np; q++) add128(&a->local[c->pivots.v[q]], per_pivot, &a->overflow);
+    }
+}
+
+/* Fig. 3 under reading R1: l path vertices precede the branch vertex, np of them
+ * pivots; I is the candidate set (the common neighbours of the whole path). */
+static void piv_rec(ctx_t* c, int32_t l, const int32_t* I, int32_t nI, int32_t np) {
+    const graph_t* g = c->g;
+    int32_t* Ip = level_buf(&c->lev, l, 0);
+    int32_t* Ipr = level_buf(&c->lev, l, 1);
+    if (!Ip || !Ipr) return;
+    /* pivot: the candidate with the most neighbours inside I (R2) */
+    int32_t p = I[0], best = -1;
+    for (int32_t i = 0; i < nI; i++) {
+        int32_t na;
+        const int32_t* a = undN(g, I[i], &na);
+        int32_t cnt = intersect(I, nI, a, na, Ip);
+        if (cnt > best) { best = cnt; p = I[i]; }
+    }
+    /* I_pruned = I - Adj(p); p itself stays (no self-loops) */
+    int32_t npr = 0, pa;
+    const int32_t* padj = undN(g, p, &pa);
+    for (int32_t i = 0; i < nI; i++)
+        if (!contains(padj, pa, I[i])) Ipr[npr++] = I[i];
+    int32_t nh = l - np;           /* holds before v */
+    for (int32_t i = 0; i < npr; i++) {
+        int32_t v = Ipr[i];
+        int32_t np2 = np + (v == p);
+        if (c->mode == MODE_K && (l + 1) - c->k > np2) continue;   /* stopping criterion */
+        int32_t na;
+        const int32_t* a = undN(g, v, &na);
+        int32_t n1 = intersect(I, nI, a, na, Ip);
+        /* drop the I_pruned vertices that come before v (R3: id order) */
+        int32_t n2 = 0;
+        for (int32_t j = 0; j < n1; j++) {
+            int32_t x = Ip[j];
+            if (x < v && contains(Ipr, npr, x)) continue;
+            Ip[n2++] = x;
+        }
+        c->acc->nodes++;
+        int ok = (v == p) ? path_set(&c->pivots, np, v) : path_set(&c->holds, nh, v);
+        if (ok) { c->lev.failed = 1; return; }
+        if (n2 > 0) piv_rec(c, l + 1, Ip, n2, np2);
+        else piv_leaf(c, nh + (v != p), np2);
+        if (c->lev.failed) return;
+    }
+}
+
+/* --------------------------------------------------------------- driver */
+
+/* Count over the given roots (all roots when roots == NULL).
+ *   scheme KCO_VC: roots are vertices (Sec. 3.2 vertex-centric);
+ *   scheme KCO_EC: roots are DAG edge indices (Sec. 3.2 edge-centric).
+ *   mode MODE_K: c_k into total; MODE_ALL: counts[] for every size;
+ *   MODE_LOCAL: per-vertex counts.
+ * The DAG (optr, ocol) and the undirected graph (uptr, ucol) share vertex ids. */
+static int run(int32_t n, const int32_t* optr, const int32_t* ocol, const int32_t* uptr,
+               const int32_t* ucol, int32_t d_max, int32_t k, int pivot, int scheme, int mode,
+               const int64_t* roots, int64_t nroots, acc_t* acc) {
+    graph_t g = {n, optr, ocol, uptr, ucol, d_max};
+    int32_t m = optr[n];
+    binom_t bn = {0, 0, 0};
+    ctx_t c;
+    memset(&c, 0, sizeof c);
+    c.g = &g; c.k = k; c.mode = mode; c.bn = &bn; c.acc = acc;
+    c.lev.width = d_max + 1;
+    if (pivot && binom_init(&bn, d_max + 2)) return KCO_ENOMEM;
+    int32_t* I = (int32_t*)malloc((size_t)(d_max + 1) * sizeof(int32_t));
+    int32_t* esrc = NULL;
+    if (scheme == KCO_EC) {
+        esrc = (int32_t*)malloc((size_t)(m ? m : 1) * sizeof(int32_t));
+        if (esrc)
+            for (int32_t u = 0; u < n; u++)
+                for (int32_t e = optr[u]; e < optr[u + 1]; e++) esrc[e] = u;
+    }
+    if (!I || (scheme == KCO_EC && !esrc)) { free(I); free(esrc); binom_free(&bn); return KCO_ENOMEM; }
+    int64_t nr = roots ? nroots : (scheme == KCO_VC ? n : m);
+    for (int64_t r = 0; r < nr && !c.lev.failed; r++) {
+        int64_t root = roots ? roots[r] : r;
+        int32_t nI, l;
+        if (scheme == KCO_VC) {
+            int32_t u = (int32_t)root, na;
+            const int32_t* a = outN(&g, u, &na);
+            memcpy(I, a, (size_t)na * sizeof(int32_t));
+            nI = na;
+            l = 1;
+            if (path_set(&c.holds, 0, u)) c.lev.failed = 1;
+        } else {
+            int32_t u = esrc[root], v = ocol[root], na, nb;
+            const int32_t* a = outN(&g, u, &na);
+            const int32_t* b = outN(&g, v, &nb);
+            nI = intersect(a, na, b, nb, I);
+            l = 2;
+            if (path_set(&c.holds, 0, u) || path_set(&c.holds, 1, v)) c.lev.failed = 1;
+        }
+        if (c.lev.failed) break;
+        if (pivot) {
+            /* hybrid (Sec. 2.3): the root level(s) are oriented, every level
+             * below pivots on the undirected adjacency; the root vertices are
+             * holds */
+            if (nI > 0) piv_rec(&c, l, I, nI, 0);
+            else piv_leaf(&c, l, 0);
+        } else if (scheme == KCO_VC) {
+            /* Fig. 2's root call: l = 2, I = N+(u) (the 2-cliques {u, v}) */
+            if (mode == MODE_ALL) { if (nI > 0) go_rec(&c, 2, I, nI); }
+            else if (k >= 3 && nI > 0) go_rec(&c, 2, I, nI);
+        } else {
+            /* edge root u->v: I = N+(u) cap N+(v) are the triangles on the edge */
+            if (mode == MODE_ALL) {
+                if (3 <= acc->cap) add128(&acc->counts[3], (u128)nI, &acc->overflow);
+                if (nI > 0) go_rec(&c, 3, I, nI);
+            } else if (k == 3) {
+                if (mode == MODE_K) {
+                    add128(&acc->total, (u128)nI, &acc->overflow);
+                } else {
+                    add128(&acc->local[c.holds.v[0]], (u128)nI, &acc->overflow);
+                    add128(&acc->local[c.holds.v[1]], (u128)nI, &acc->overflow);
+                    for (int32_t j = 0; j < nI; j++) add128(&acc->local[I[j]], 1, &acc->overflow);
+                }
+            } else if (k > 3 && nI > 0) {
+                go_rec(&c, 3, I, nI);
+            }
+        }
+    }
+    int failed = c.lev.failed;
+    levels_free(&c.lev);
+    free(c.holds.v); free(c.pivots.v);
+    free(esrc); free(I); binom_free(&bn);
+    return failed ? KCO_ENOMEM : KCO_OK;
+}
+
+/* c_k over the given roots (all roots when roots == NULL).  Result as two u64
+ * halves; returns KCO_EOVERFLOW when the true value needs more than 128 bits.
+ * k = 1 and k = 2 follow R6 when roots == NULL.  *nodes receives the number of
+ * tree nodes visited (intersections with an adjacency list). */
+int kco_count(int32_t n, const int32_t* optr, const int32_t* ocol, const int32_t* uptr,
+              const int32_t* ucol, int32_t d_max, int32_t k, int pivot, int scheme,
+              const int64_t* roots, int64_t nroots, uint64_t* out_lo, uint64_t* out_hi,
+              uint64_t* nodes) {
+    if (k < 1 || (scheme != KCO_VC && scheme != KCO_EC)) return KCO_EINVAL;
+    acc_t acc;
+    memset(&acc, 0, sizeof acc);
+    int st = KCO_OK;
+    if (k == 1 && !roots) acc.total = (u128)n;
+    else if (k == 2 && !roots) acc.total = (u128)optr[n];
+    else st = run(n, optr, ocol, uptr, ucol, d_max, k, pivot, scheme, MODE_K, roots, nroots, &acc);
+    *out_lo = (uint64_t)acc.total;
+    *out_hi = (uint64_t)(acc.total >> 64);
+    if (nodes) *nodes = acc.nodes;
+    if (st) return st;
+    return acc.overflow ? KCO_EOVERFLOW : KCO_OK;
+}
+
+/* counts[j] = c_j for j = 0..cap (as lo/hi pairs, 2*(cap+1) u64).  counts[0] = 1,
+ * counts[1] = n, counts[2] = m; the rest come from the traversal with no k bound. */
+int kco_count_all(int32_t n, const int32_t* optr, const int32_t* ocol, const int32_t* uptr,
+                  const int32_t* ucol, int32_t d_max, int pivot, int scheme, int32_t cap,
+                  uint64_t* counts, int32_t* omega) {
+    if (cap < 2 || (scheme != KCO_VC && scheme != KCO_EC)) return KCO_EINVAL;
+    acc_t acc;
+    memset(&acc, 0, sizeof acc);
+    acc.cap = cap;
+    acc.counts = (u128*)calloc((size_t)cap + 1, sizeof(u128));
+    if (!acc.counts) return KCO_ENOMEM;
+    int st = run(n, optr, ocol, uptr, ucol, d_max, 0, pivot, scheme, MODE_ALL, NULL, 0, &acc);
+    acc.counts[0] = 1;
+    acc.counts[1] = (u128)n;
+    acc.counts[2] = (u128)optr[n];
+    int32_t om = n > 0 ? 1 : 0;
+    for (int32_t j = 0; j <= cap; j++) {
+        counts[2 * j] = (uint64_t)acc.counts[j];
+        counts[2 * j + 1] = (uint64_t)(acc.counts[j] >> 64);
+        if (j > 0 && acc.counts[j] != 0) om = j;
+    }
+    *omega = om;
+    free(acc.counts);
+    if (st) return st;
+    return acc.overflow ? KCO_EOVERFLOW : KCO_OK;
+}
+
+/* local[v] = number of k-cliques containing v (lo/hi pairs, 2n u64). */
+int kco_count_local(int32_t n, const int32_t* optr, const int32_t* ocol, const int32_t* uptr,
+                    const int32_t* ucol, int32_t d_max, int32_t k, int pivot, int scheme,
+                    uint64_t* local) {
+    if (k < 1 || (scheme != KCO_VC && scheme != KCO_EC)) return KCO_EINVAL;
+    acc_t acc;
+    memset(&acc, 0, sizeof acc);
+    acc.local = (u128*)calloc((size_t)(n ? n : 1), sizeof(u128));
+    if (!acc.local) return KCO_ENOMEM;
+    int st = KCO_OK;
+    if (k == 1) {
+        for (int32_t v = 0; v < n; v++) acc.local[v] = 1;
+    } else if (k == 2) {
+        for (int32_t v = 0; v < n; v++) acc.local[v] = (u128)(uptr[v + 1] - uptr[v]);
+    } else {
+        st = run(n, optr, ocol, uptr, ucol, d_max, k, pivot, scheme, MODE_LOCAL, NULL, 0, &acc);
+    }
+    for (int32_t v = 0; v < n; v++) {
+        local[2 * v] = (uint64_t)acc.local[v];
+        local[2 * v + 1] = (uint64_t)(acc.local[v] >> 64);
+    }
+    free(acc.local);
+    if (st) return st;
+    return acc.overflow ? KCO_EOVERFLOW : KCO_OK;
+}
