@@ -1,0 +1,144 @@
+/*
+ * kc.h -- exact k-clique counting on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Almasri, El Hajj, Nagi, Xiong, Hwu, "Parallel K-clique Counting on
+ * GPUs", ICS 2022 (arXiv 2104.13209).  The problem (Sec. 1): given an undirected
+ * simple graph G and an integer k, return the number of k-vertex subsets of V
+ * whose vertices are pairwise adjacent.
+ *
+ * Pipeline behind this header:
+ *   kc_orient   orient G into a DAG by degree or degeneracy order (Sec. 3.1),
+ *               filter edges and rebuild the CSR by histogram + exclusive scan;
+ *   kc_count    traverse one search tree per root vertex (vertex-centric) or root
+ *               edge (edge-centric) (Sec. 3.2) over the root's induced sub-graph
+ *               encoded as bitsets (Sec. 2.4, 3.4), without pivoting (Fig. 2) or
+ *               with pivoting (Fig. 3);
+ *   kc_count_all  counts for every clique size at once (Sec. 2.3: pivoting counts
+ *               all k in one traversal).
+ *
+ * Conventions for every entry point
+ *   - Pointers inside kc_csr / kc_dag and the workspace are DEVICE pointers,
+ *     allocated and freed by the caller; the library never allocates device
+ *     memory in these calls and never frees caller memory.  Result pointers
+ *     (kc_u128*, int32_t*) passed as separate arguments are HOST pointers.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *     it; calls that return a value to the host synchronise that stream.
+ *   - Every call returns a kc_status; no exception or abort crosses the ABI.
+ *   - Vertex ids are int32 in [0, n); CSR offsets are int32 (nnz < 2^31).
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KC_API __attribute__((visibility("default")))
+
+/* Exact unsigned 128-bit count: value = lo + 2^64 * hi. */
+typedef struct kc_u128 { uint64_t lo, hi; } kc_u128;
+
+typedef enum kc_status {
+    KC_OK = 0,
+    KC_EINVAL = -1,        /* bad argument or malformed graph (when validated)   */
+    KC_ENOMEM = -2,        /* workspace too small                                */
+    KC_EOVERFLOW = -3,     /* count does not fit the result width                */
+    KC_EDEVICE = -4,       /* a HIP runtime call failed                          */
+    KC_ECANCELED = -5,     /* reserved                                           */
+    KC_EUNSUPPORTED = -6   /* graph exceeds a documented limit of this build     */
+} kc_status;
+
+enum { KC_ORDER_DEGREE = 0, KC_ORDER_DEGENERACY = 1 };
+enum { KC_SCHEME_AUTO = 0, KC_SCHEME_VC = 1, KC_SCHEME_EC = 2 };
+
+/* Largest root candidate set (out-degree) the traversal kernels support: the
+ * root's bitset rows live in LDS, s x ceil(s/32) words.  kc_count returns
+ * KC_EUNSUPPORTED when the DAG's d_max exceeds it. */
+#define KC_MAX_DMAX 1024
+
+/* Undirected input graph (Sec. 3.1 CSR): row_ptr[n+1], col[nnz], each row
+ * strictly increasing, no self-loops, symmetric (u in row v iff v in row u).
+ * Device pointers, read only. */
+typedef struct kc_csr {
+    int32_t n;
+    int32_t nnz;               /* = 2m */
+    const int32_t* row_ptr;
+    const int32_t* col;
+} kc_csr;
+
+/* Oriented graph (DAG) written by kc_orient.  Vertices are RELABELLED by their
+ * position in the orientation order: DAG vertex i is input vertex perm[i], and
+ * every edge i -> j has i < j.  Out-lists are sorted ascending (Sec. 3.4 assigns
+ * bit positions in a fixed sorted vertex order; with this labelling a root's
+ * bitset rows are upper triangular).  Caller-allocated device arrays:
+ *   row_ptr[n+1], col[m], src[m] (COO source of each edge, Sec. 3.1 hybrid
+ *   CSR + COO for edge-centric roots), perm[n].
+ * n, m, d_max (max out-degree), degeneracy (-1 for degree order) and order are
+ * host fields filled by kc_orient. */
+typedef struct kc_dag {
+    int32_t n, m, d_max, degeneracy, order;
+    int32_t* row_ptr;
+    int32_t* col;
+    int32_t* src;
+    int32_t* perm;
+} kc_dag;
+
+/* Tuning options; NULL means defaults.  scheme: KC_SCHEME_*; width: lanes per
+ * sub-wavefront group (1, 2, 4, 8, 16, 32 or 64; 0 = auto) (Sec. 3.5).
+ * test_preload: added to the internal accumulator before counting; it exists
+ * only so that tests can drive the 64-bit overflow path, and is 0 in normal use. */
+typedef struct kc_opts {
+    int32_t scheme;
+    int32_t width;
+    int32_t reserved0;
+    int32_t reserved1;
+    uint64_t test_preload;
+} kc_opts;
+
+/* Bytes of device workspace kc_orient needs for this input size and order. */
+KC_API size_t kc_orient_workspace(int32_t n, int32_t nnz, int32_t order);
+
+/* Orient g (Sec. 3.1).  order: KC_ORDER_DEGREE (edge u->v iff (deg u, u) <
+ * (deg v, v)) or KC_ORDER_DEGENERACY (k-core removal order from GPU peeling in
+ * level-synchronous rounds; ties inside a round by id).  Fills *out (device
+ * arrays must hold n+1, m, m and n int32 with m = nnz/2) and its host fields;
+ * synchronises `stream`.  validate != 0 first checks that g is a sorted simple
+ * symmetric CSR and returns KC_EINVAL if not; with validate == 0 a malformed
+ * graph gives an unspecified DAG.  Returns KC_ENOMEM if ws_bytes is below
+ * kc_orient_workspace(). */
+KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out, void* ws,
+                         size_t ws_bytes, int32_t validate, void* stream);
+
+/* Bytes of device workspace kc_count / kc_count_all need for this DAG. */
+KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t pivot, const kc_opts* o);
+
+/* Number of k-cliques of the DAG's graph into *count (host).
+ *   pivot == 0: graph-orientation traversal (Fig. 2); the result is a 64-bit
+ *               count (count->hi == 0) and KC_EOVERFLOW is returned when the true
+ *               count is 2^64 or more.
+ *   pivot != 0: hybrid pivoting traversal (Fig. 3, Sec. 2.3); 128-bit count,
+ *               KC_EOVERFLOW at 2^128 or more.
+ * k < 1 is KC_EINVAL; k = 1 gives n and k = 2 gives m.  Synchronises `stream`. */
+KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
+                        size_t ws_bytes, const kc_opts* o, void* stream);
+
+/* counts[j] = number of j-cliques for j = 0..cap (host array of cap+1), with
+ * counts[0] = 1 (the empty clique), counts[1] = n, counts[2] = m; *omega = the
+ * largest j with counts[j] > 0 (the clique number).  pivot != 0 uses pivoting
+ * (Sec. 2.3); pivot == 0 walks the orientation tree with no depth bound.
+ * Returns KC_EINVAL if cap < 2 and KC_EOVERFLOW if a count needs more than 128
+ * bits.  Synchronises `stream`. */
+KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,
+                            int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
+                            void* stream);
+
+/* Static text for a status code. */
+KC_API const char* kc_strerror(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KC_H */

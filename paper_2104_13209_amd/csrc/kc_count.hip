@@ -1,0 +1,526 @@
+// k-clique counting by search-tree traversal over bitset-encoded induced
+// sub-graphs (paper Sec. 2.2 Fig. 2, Sec. 3.2 - 3.6), for gfx950 wave64.
+//
+// Work distribution (Sec. 3.2, 3.6): persistent workgroups pull roots from a
+// device work queue.  A root is a vertex u (vertex-centric, VC) or a DAG edge
+// u->v (edge-centric, EC).  Roots are split by the size bound of their candidate
+// set S into a light list (|S| <= 64: one wavefront per root) and a heavy list
+// (one 4-wavefront workgroup per root); roots whose S cannot hold k - |path|
+// vertices are dropped.
+//
+// Extraction (Sec. 2.4, 3.4): S = N+(u) (VC) or N+(u) cap N+(v) (EC), kept
+// sorted, so with the DAG's order-relabelled ids bit j of row i means S[j] is an
+// out-neighbour of S[i], and only j > i can be set (upper-triangular rows).  Row
+// bits come from binary searches of each out-neighbour in S (the paper's
+// binary-search intersections).
+//
+// Traversal (Fig. 2 with the intra-block split of Sec. 3.2 and sub-warp groups
+// of Sec. 3.5): the lanes of a wavefront form groups of G lanes; a group owns one
+// subtree at a time (task i = the branch through S[i]), taken dynamically from an
+// LDS counter, and walks it depth-first with an explicit stack (Sec. 3.3).  Each
+// lane holds words glane, glane + G, ... of the current level's remaining set R.
+// One step: the lowest set bit v of R is found with a ballot and one bpermute,
+// cleared, and Y = R & B[v] is formed.  Because rows are upper triangular,
+// R & B[v] (R holding only bits above v) equals I cap Adj(v) of Fig. 2.  At the
+// last level the step adds popcount(Y); otherwise a non-empty Y is pushed.
+// Every lane keeps its own 64-bit partial count; wavefronts reduce them exactly
+// into a 128-bit device counter when they exit.
+#include <climits>
+
+#include "kc_internal.h"
+
+namespace kc {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kLightCap = 64;       // |S| bound of the light list
+
+enum CountCtl {
+    CC_LIGHT_N = 0,    // light root count
+    CC_HEAVY_N = 1,    // heavy root count
+    CC_LIGHT_HEAD = 2, // light queue head
+    CC_HEAVY_HEAD = 3, // heavy queue head
+    CC_WORDS = 8
+};
+
+struct GoParams {
+    int n, m, k;
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ col;
+    const int* __restrict__ src;
+    const int* __restrict__ roots;   // root ids of this list
+    const int* __restrict__ nroots;  // device count of this list
+    int* head;                       // device queue head of this list
+    unsigned long long* acc;         // [lo, hi]
+    int s_cap;                       // LDS rows per team
+    int levels;                      // stack levels per group
+};
+
+__device__ __forceinline__ int ffs64(unsigned long long x) { return __ffsll(static_cast<long long>(x)) - 1; }
+
+// Sizes of the per-team LDS regions, in 32-bit words.
+struct TeamLayout {
+    int s_words, b_stride, b_words, stack_words, total;
+};
+
+__host__ __device__ constexpr int b_stride_of(int maxw) { return (maxw > 1 && (maxw % 2) == 0) ? maxw + 1 : maxw; }
+
+__host__ __device__ inline TeamLayout team_layout(int s_cap, int maxw, int groups, int levels) {
+    TeamLayout t;
+    t.s_words = s_cap;
+    t.b_stride = b_stride_of(maxw);
+    t.b_words = s_cap * t.b_stride;
+    t.stack_words = groups * levels * maxw;
+    t.total = 8 + t.s_words + t.b_words + t.stack_words;
+    return t;
+}
+
+// ------------------------------------------------------------ classify
+
+// Split roots into light / heavy lists by the bound on |S|; drop roots that
+// cannot contain a k-clique (|S| < k - 1 for VC, < k - 2 for EC).
+template <bool EC>
+__global__ void __launch_bounds__(kBlock) k_classify(int nroots_total, int k, const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col, const int* __restrict__ src,
+                                                    int* light, int* heavy, int* ctl) {
+    const int lane = threadIdx.x & 63;
+    const int need = EC ? k - 2 : k - 1;
+    for (int base = blockIdx.x * blockDim.x; base < nroots_total; base += gridDim.x * blockDim.x) {
+        int r = base + threadIdx.x;
+        int bound = -1;
+        if (r < nroots_total) {
+            if (EC) {
+                int u = src[r], v = col[r];
+                int du = row_ptr[u + 1] - row_ptr[u] - 1;
+                int dv = row_ptr[v + 1] - row_ptr[v];
+                bound = du < dv ? du : dv;
+            } else {
+                bound = row_ptr[r + 1] - row_ptr[r];
+            }
+        }
+        bool ok = r < nroots_total && bound >= need && bound >= 0;
+        bool is_light = ok && bound <= kLightCap;
+        bool is_heavy = ok && bound > kLightCap;
+        unsigned long long ml = __ballot(is_light), mh = __ballot(is_heavy);
+        int bl = 0, bh = 0;
+        if (lane == 0) {
+            if (ml) bl = atomicAdd(&ctl[CC_LIGHT_N], __popcll(ml));
+            if (mh) bh = atomicAdd(&ctl[CC_HEAVY_N], __popcll(mh));
+        }
+        bl = __shfl(bl, 0);
+        bh = __shfl(bh, 0);
+        if (is_light) light[bl + __popcll(ml & lanemask_lt())] = r;
+        if (is_heavy) heavy[bh + __popcll(mh & lanemask_lt())] = r;
+    }
+}
+
+// ------------------------------------------------------------- team sync
+
+template <int TW>
+__device__ __forceinline__ void team_sync() {
+    if (TW == 1) wave_sync_lds();
+    else __syncthreads();
+}
+
+// ------------------------------------------------------------- traversal
+
+// G: lanes per group; MAXW: bitset words per row this instantiation handles;
+// TW: wavefronts per team (1 = wave per root, 4 = workgroup per root).
+template <int G, int MAXW, int TW, bool EC>
+__global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "group size");
+    constexpr int WPL = (MAXW + G - 1) / G;             // words per lane
+    constexpr int TEAM_LANES = 64 * TW;
+    constexpr int GROUPS = TEAM_LANES / G;              // groups per team
+    constexpr int XG = 16;                              // lanes per row during extraction
+    extern __shared__ unsigned int lds[];
+
+    const int lane = threadIdx.x & 63;
+    const int team = threadIdx.x / TEAM_LANES;
+    const int tl = threadIdx.x % TEAM_LANES;            // lane within team
+    const int glane = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const int group = tl / G;
+    const unsigned long long gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gbase);
+
+    const TeamLayout L = team_layout(P.s_cap, MAXW, GROUPS, P.levels);
+    unsigned int* tbase = lds + team * L.total;
+    int* ctl = reinterpret_cast<int*>(tbase);           // [0] task ctr, [1] s, [2] root
+    int* S = reinterpret_cast<int*>(tbase + 8);
+    unsigned int* B = tbase + 8 + L.s_words;
+    unsigned int* stack = B + L.b_words + group * P.levels * MAXW;
+    const int stride = L.b_stride;
+    const int k = P.k;
+    const int p0 = EC ? 3 : 2;                          // path length of a task's root branch
+    const int nroots = *P.nroots;
+
+    unsigned long long acc = 0;
+
+    for (;;) {
+        // ---- fetch a root
+        if (tl == 0) ctl[2] = atomicAdd(P.head, 1);
+        team_sync<TW>();
+        const int root = ctl[2];
+        if (root >= nroots) break;
+        const int rid = P.roots[root];
+
+        // ---- candidate set S (sorted)
+        if (!EC) {
+            const int b = P.row_ptr[rid], e = P.row_ptr[rid + 1];
+            for (int j = tl; j < e - b; j += TEAM_LANES) S[j] = P.col[b + j];
+            if (tl == 0) ctl[1] = e - b;
+        } else if (tl < 64) {
+            // one wavefront intersects N+(v) with N+(u) (ordered compaction)
+            const int u = P.src[rid], v = P.col[rid];
+            const int ub = P.row_ptr[u], ue = P.row_ptr[u + 1];
+            const int vb = P.row_ptr[v], ve = P.row_ptr[v + 1];
+            int cnt = 0;
+            for (int j0 = vb; j0 < ve; j0 += 64) {
+                const int j = j0 + lane;
+                bool hit = false;
+                int x = 0;
+                if (j < ve) {
+                    x = P.col[j];
+                    int lo = ub, hi = ue;
+                    while (lo < hi) {
+                        int mid = (lo + hi) >> 1;
+                        if (P.col[mid] < x) lo = mid + 1; else hi = mid;
+                    }
+                    hit = lo < ue && P.col[lo] == x;
+                }
+                unsigned long long mk = __ballot(hit);
+                if (hit) S[cnt + __popcll(mk & lanemask_lt())] = x;
+                cnt += __popcll(mk);
+            }
+            if (lane == 0) ctl[1] = cnt;
+        }
+        team_sync<TW>();
+        const int s = ctl[1];
+        if (EC && k == 3) {
+            // every vertex of S closes a triangle with the root edge
+            if (tl == 0) acc += static_cast<unsigned long long>(s);
+            team_sync<TW>();
+            continue;
+        }
+
+        // ---- bitset rows: B[i] bit j  <=>  S[j] in N+(S[i])
+        for (int w = tl; w < s * stride; w += TEAM_LANES) B[w] = 0u;
+        if (tl == 0) ctl[0] = 0;
+        team_sync<TW>();
+        const int smax = s > 0 ? S[s - 1] : 0;
+        for (int i = tl / XG; i < s; i += TEAM_LANES / XG) {
+            const int w = S[i];
+            const int b = P.row_ptr[w], e = P.row_ptr[w + 1];
+            for (int j = b + (tl % XG); j < e; j += XG) {
+                const int x = P.col[j];
+                if (x > smax) break;                    // rows are sorted: nothing further is in S
+                int lo = i + 1, hi = s;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (S[mid] < x) lo = mid + 1; else hi = mid;
+                }
+                if (lo < s && S[lo] == x) atomicOr(&B[i * stride + (lo >> 5)], 1u << (lo & 31));
+            }
+        }
+        team_sync<TW>();
+
+        // ---- traversal: groups take subtrees (tasks i = 0..s-1) dynamically
+        unsigned int R[WPL];
+#pragma unroll
+        for (int t = 0; t < WPL; t++) R[t] = 0u;
+        int depth = 0, p = p0;
+        bool done = false;
+        for (;;) {
+            bool my_any = false;
+#pragma unroll
+            for (int t = 0; t < WPL; t++) my_any |= R[t] != 0u;
+            const bool has = (__ballot(my_any) & gmask) != 0ull;
+            const bool need = !has && !done;
+            const bool fetch = need && depth == 0;
+            if (need && depth > 0) {
+                // pop
+                depth--;
+                p--;
+#pragma unroll
+                for (int t = 0; t < WPL; t++) {
+                    const int wd = glane + t * G;
+                    R[t] = wd < MAXW ? stack[depth * MAXW + wd] : 0u;
+                }
+            }
+            int task = 0;
+            if (fetch && glane == 0) task = atomicAdd(&ctl[0], 1);
+            task = __shfl(task, gbase);
+            if (fetch) {
+                if (task < s) {
+                    p = p0;
+                    unsigned int c = 0;
+#pragma unroll
+                    for (int t = 0; t < WPL; t++) {
+                        const int wd = glane + t * G;
+                        R[t] = wd < MAXW ? B[task * stride + wd] : 0u;
+                        c += __popc(R[t]);
+                    }
+                    if (p0 + 1 == k) {
+                        acc += c;
+#pragma unroll
+                        for (int t = 0; t < WPL; t++) R[t] = 0u;
+                    }
+                } else {
+                    done = true;
+                }
+            }
+            if (__ballot(!done) == 0ull) break;
+            if (!has) continue;   // popped or fetched: re-evaluate next step
+
+            // ---- expand: lowest set bit of R over the group
+            int tsel = WPL;
+            int owner = gbase;
+#pragma unroll
+            for (int t = WPL - 1; t >= 0; t--) {
+                const unsigned long long bt = __ballot(R[t] != 0u) & gmask;
+                if (bt) { tsel = t; owner = ffs64(bt); }
+            }
+            unsigned int mine = 0u;
+#pragma unroll
+            for (int t = 0; t < WPL; t++) mine = (t == tsel) ? R[t] : mine;
+            const unsigned int wv = static_cast<unsigned int>(__shfl(static_cast<int>(mine), owner));
+            const int v = ((owner - gbase) + tsel * G) * 32 + (__ffs(wv) - 1);
+            if (lane == owner) {
+#pragma unroll
+                for (int t = 0; t < WPL; t++)
+                    if (t == tsel) R[t] &= R[t] - 1u;
+            }
+            unsigned int Y[WPL];
+            bool y_any = false;
+            unsigned int c = 0;
+#pragma unroll
+            for (int t = 0; t < WPL; t++) {
+                const int wd = glane + t * G;
+                Y[t] = (wd < MAXW && R[t]) ? (R[t] & B[v * stride + wd]) : 0u;
+                y_any |= Y[t] != 0u;
+                c += __popc(Y[t]);
+            }
+            if (p + 2 == k) {
+                acc += c;
+            } else {
+                const bool push = (__ballot(y_any) & gmask) != 0ull;
+                if (push) {
+#pragma unroll
+                    for (int t = 0; t < WPL; t++) {
+                        const int wd = glane + t * G;
+                        if (wd < MAXW) stack[depth * MAXW + wd] = R[t];
+                        R[t] = Y[t];
+                    }
+                    depth++;
+                    p++;
+                }
+            }
+        }
+        team_sync<TW>();
+    }
+
+    unsigned long long lo, hi;
+    wave_sum_u128(acc, lo, hi);
+    if (lane == 0) atomic_add_u128(P.acc, P.acc + 1, lo, hi);
+}
+
+// --------------------------------------------------------------- launch
+
+struct CountWs {
+    int* ctl;
+    unsigned long long* acc;
+    int* light;
+    int* heavy;
+};
+
+CountWs carve_count(void* ws, int nroots_max, size_t* bytes) {
+    Carver c(ws);
+    CountWs w;
+    w.ctl = c.take<int>(CC_WORDS);
+    w.acc = c.take<unsigned long long>(4);
+    w.light = c.take<int>(static_cast<size_t>(nroots_max > 0 ? nroots_max : 1));
+    w.heavy = c.take<int>(static_cast<size_t>(nroots_max > 0 ? nroots_max : 1));
+    *bytes = c.bytes();
+    return w;
+}
+
+int levels_for(int k, bool ec) {
+    const int p0 = ec ? 3 : 2;
+    int lv = k - 2 - p0;
+    return lv < 1 ? 1 : lv;
+}
+
+template <int G, int MAXW, int TW, bool EC>
+int launch_go(const GoParams& base, int s_cap, hipStream_t s) {
+    constexpr int TEAMS = kWavesPerBlock / TW;
+    constexpr int GROUPS = 64 * TW / G;
+    GoParams P = base;
+    P.s_cap = s_cap;
+    P.levels = levels_for(P.k, EC);
+    const TeamLayout L = team_layout(s_cap, MAXW, GROUPS, P.levels);
+    const size_t lds_bytes = static_cast<size_t>(L.total) * TEAMS * sizeof(unsigned int);
+    if (lds_bytes > 160 * 1024) return KC_EUNSUPPORTED;
+    auto kern = k_go<G, MAXW, TW, EC>;
+    if (lds_bytes > 64 * 1024)
+        KC_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)));
+    int occ = 0;
+    KC_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBlock, lds_bytes));
+    if (occ < 1) return KC_EUNSUPPORTED;
+    const int blocks = device_cus() * occ;
+    kern<<<blocks, kBlock, lds_bytes, s>>>(P);
+    KC_CHECK(hipGetLastError());
+    return KC_OK;
+}
+
+template <bool EC>
+int launch_light(const GoParams& P, int width, hipStream_t s) {
+    switch (width) {
+        case 1: return launch_go<1, 2, 1, EC>(P, kLightCap, s);
+        case 2: return launch_go<2, 2, 1, EC>(P, kLightCap, s);
+        case 4: return launch_go<4, 2, 1, EC>(P, kLightCap, s);
+        case 8: return launch_go<8, 2, 1, EC>(P, kLightCap, s);
+        default: return KC_EINVAL;
+    }
+}
+
+template <bool EC, int MAXW>
+int launch_heavy_w(const GoParams& P, int width, int s_cap, hipStream_t s) {
+    switch (width) {
+        case 4: return launch_go<4, MAXW, 4, EC>(P, s_cap, s);
+        case 8: return launch_go<8, MAXW, 4, EC>(P, s_cap, s);
+        case 16: return launch_go<16, MAXW, 4, EC>(P, s_cap, s);
+        case 32: return launch_go<32, MAXW, 4, EC>(P, s_cap, s);
+        default: return KC_EINVAL;
+    }
+}
+
+template <bool EC>
+int launch_heavy(const GoParams& P, int width, int d_max, hipStream_t s) {
+    const int s_cap = ((d_max + 31) / 32) * 32;
+    if (d_max <= 128) return launch_heavy_w<EC, 4>(P, width, s_cap, s);
+    if (d_max <= 256) return launch_heavy_w<EC, 8>(P, width, s_cap, s);
+    if (d_max <= 512) return launch_heavy_w<EC, 16>(P, width, s_cap, s);
+    return launch_heavy_w<EC, 32>(P, width, s_cap, s);
+}
+
+bool valid_dag(const kc_dag* d) {
+    if (!d || d->n < 0 || d->m < 0 || d->d_max < 0) return false;
+    if (!d->row_ptr) return false;
+    if (d->m > 0 && (!d->col || !d->src)) return false;
+    return true;
+}
+
+int pick_scheme(const kc_opts* o, int k) {
+    int sc = o ? o->scheme : KC_SCHEME_AUTO;
+    if (sc == KC_SCHEME_AUTO) sc = k < 6 ? KC_SCHEME_VC : KC_SCHEME_EC;   // Sec. 4.5 guideline
+    return sc;
+}
+
+int pick_width(const kc_opts* o, int d_max, bool light) {
+    int w = o ? o->width : 0;
+    if (w == 0) {
+        if (light) return 2;
+        return d_max < 200 ? 4 : 8;   // Sec. 4.5: small groups for small d_max, 8 otherwise
+    }
+    return w;
+}
+
+}  // namespace
+}  // namespace kc
+
+using namespace kc;
+
+extern "C" KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t pivot, const kc_opts* o) {
+    (void)k;
+    (void)pivot;
+    (void)o;
+    if (!d) return 0;
+    size_t bytes = 0;
+    const int nr = d->m > d->n ? d->m : d->n;
+    carve_count(nullptr, nr, &bytes);
+    return bytes;
+}
+
+extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
+                                   size_t ws_bytes, const kc_opts* o, void* stream) {
+    if (!valid_dag(d) || !count || k < 1) return KC_EINVAL;
+    count->lo = count->hi = 0;
+    const unsigned long long preload = o ? o->test_preload : 0ull;
+    if (k == 1 || k == 2) {
+        unsigned long long v = (k == 1 ? static_cast<unsigned long long>(d->n) : static_cast<unsigned long long>(d->m));
+        unsigned long long sum = v + preload;
+        count->lo = sum;
+        count->hi = sum < v ? 1ull : 0ull;
+        if (!pivot && count->hi) { count->hi = 0; return KC_EOVERFLOW; }
+        return KC_OK;
+    }
+    if (pivot) return KC_EUNSUPPORTED;
+    if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    size_t need = 0;
+    const int nr_max = d->m > d->n ? d->m : d->n;
+    CountWs w = carve_count(ws, nr_max, &need);
+    if (!ws || ws_bytes < need) return KC_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (k > d->d_max + 1 || d->m == 0) {
+        count->lo = preload;
+        return KC_OK;
+    }
+    const int scheme = pick_scheme(o, k);
+    if (scheme != KC_SCHEME_VC && scheme != KC_SCHEME_EC) return KC_EINVAL;
+    const bool ec = scheme == KC_SCHEME_EC;
+    const int nroots = ec ? d->m : d->n;
+
+    KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
+    unsigned long long init[4] = {preload, 0ull, 0ull, 0ull};
+    KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
+
+    const int cblocks = div_up(nroots, kBlock) < device_cus() * 8 ? div_up(nroots, kBlock) : device_cus() * 8;
+    if (ec)
+        k_classify<true><<<cblocks, kBlock, 0, s>>>(nroots, k, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
+    else
+        k_classify<false><<<cblocks, kBlock, 0, s>>>(nroots, k, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
+    KC_CHECK(hipGetLastError());
+
+    GoParams P;
+    P.n = d->n;
+    P.m = d->m;
+    P.k = k;
+    P.row_ptr = d->row_ptr;
+    P.col = d->col;
+    P.src = d->src;
+    P.acc = w.acc;
+    P.s_cap = 0;
+    P.levels = 0;
+
+    P.roots = w.light;
+    P.nroots = w.ctl + CC_LIGHT_N;
+    P.head = w.ctl + CC_LIGHT_HEAD;
+    int st = ec ? launch_light<true>(P, pick_width(o, d->d_max, true) > 8 ? 8 : pick_width(o, d->d_max, true), s)
+                : launch_light<false>(P, pick_width(o, d->d_max, true) > 8 ? 8 : pick_width(o, d->d_max, true), s);
+    if (st != KC_OK) return st;
+    if (d->d_max > kLightCap) {
+        P.roots = w.heavy;
+        P.nroots = w.ctl + CC_HEAVY_N;
+        P.head = w.ctl + CC_HEAVY_HEAD;
+        int wd = pick_width(o, d->d_max, false);
+        if (wd < 4) wd = 4;
+        st = ec ? launch_heavy<true>(P, wd, d->d_max, s) : launch_heavy<false>(P, wd, d->d_max, s);
+        if (st != KC_OK) return st;
+    }
+    unsigned long long res[2];
+    KC_CHECK(hipMemcpyAsync(res, w.acc, sizeof(res), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipStreamSynchronize(s));
+    count->lo = res[0];
+    count->hi = 0;
+    if (res[1] != 0) return KC_EOVERFLOW;
+    return KC_OK;
+}
+
+extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,
+                                       int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
+                                       void* stream) {
+    (void)d; (void)pivot; (void)counts; (void)cap; (void)omega; (void)ws; (void)ws_bytes; (void)o; (void)stream;
+    return KC_EUNSUPPORTED;
+}

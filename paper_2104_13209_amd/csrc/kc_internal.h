@@ -1,0 +1,119 @@
+// Internal helpers shared by the HIP sources of libkc (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kc.h"
+
+#define KC_CHECK(call)                                   \
+    do {                                                 \
+        hipError_t kc_err_ = (call);                     \
+        if (kc_err_ != hipSuccess) return KC_EDEVICE;    \
+    } while (0)
+
+namespace kc {
+
+constexpr int kWave = 64;
+
+// Workspace carving: consecutive 256-byte aligned slices of one caller buffer.
+struct Carver {
+    char* base;
+    size_t off;
+    explicit Carver(void* b) : base(static_cast<char*>(b)), off(0) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
+inline int div_up(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
+
+// Number of compute units of the current device (cached per process).
+int device_cus();
+
+// ------------------------------------------------------------- device side
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Coherent (L2) load of a value other workgroups update with atomics.
+template <class T>
+__device__ __forceinline__ T ld_acquire(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exact unsigned 128-bit accumulation into device memory: lo receives x and a
+// carry out of lo goes to hi (both 64-bit atomics, so the sum is exact).
+__device__ __forceinline__ void atomic_add_u128(unsigned long long* lo, unsigned long long* hi,
+                                                unsigned long long x_lo, unsigned long long x_hi) {
+    if (x_lo) {
+        unsigned long long old = atomicAdd(lo, x_lo);
+        if (old + x_lo < old) x_hi += 1;
+    }
+    if (x_hi) atomicAdd(hi, x_hi);
+}
+
+// Wave-wide sum of a per-lane u64 into (lo, hi): exact, with carry detection.
+__device__ __forceinline__ void wave_sum_u128(unsigned long long v, unsigned long long& lo,
+                                              unsigned long long& hi) {
+    unsigned long long carry = 0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, kWave);
+        unsigned long long oc = __shfl_xor(carry, off, kWave);
+        unsigned long long s = v + o;
+        carry += oc + (s < v ? 1ull : 0ull);
+        v = s;
+    }
+    lo = v;
+    hi = carry;
+}
+
+}  // namespace kc
+
+namespace kc {
+
+// Make this wave's LDS writes visible to its other lanes before they read.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    unsigned l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        T o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        T o = __shfl_xor(v, off, kWave);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+}  // namespace kc

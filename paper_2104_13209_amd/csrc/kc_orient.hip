@@ -1,0 +1,555 @@
+// Orientation and CSR rebuild on the GPU (paper Sec. 3.1).
+//
+// Steps, all on one stream:
+//   validate  (optional) sorted, simple, symmetric CSR check
+//   key       degree order: key(v) = deg(v)
+//             degeneracy order: key(v) = peeling round of v (k-core removal
+//             order computed by level-synchronous peeling, one cooperative kernel)
+//   sort      stable LSD radix sort of vertex ids by key: the position in the
+//             sorted order is the new id, so (key, old id) order is the orientation
+//   filter    per vertex, keep neighbours with a larger new id; out-degree
+//             histogram, exclusive scan -> row_ptr (the paper's histogram + scan)
+//   compact   gather each kept row, sort it by new id, write col and the COO src
+#include <hip/hip_cooperative_groups.h>
+
+#include <climits>
+
+#include "kc_internal.h"
+
+namespace cg = cooperative_groups;
+
+namespace kc {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 8;                       // scan items per thread
+constexpr int kTile = kBlock * kItems;          // 2048 elements per scan tile
+constexpr int kRowCap = KC_MAX_DMAX;            // rows sorted in LDS up to this length
+
+// Control words in the orientation workspace.
+enum Ctl {
+    CTL_ERR = 0,       // validation error flag
+    CTL_MAXKEY = 1,    // largest sort key
+    CTL_DMAX = 2,      // max out-degree
+    CTL_DEGEN = 3,     // degeneracy (peel)
+    CTL_ROUNDS = 4,    // peel rounds
+    CTL_LONG = 5,      // a row longer than kRowCap exists
+    CTL_ZEROS = 6,     // zero count of the current radix pass
+    CTL_SIZE0 = 8,     // peel frontier sizes, ring of 3 (8, 9, 10)
+    CTL_MIN = 11,      // peel level minimum
+    CTL_WORDS = 16
+};
+
+// ------------------------------------------------------------ validation
+
+// One wave per vertex.  Every index is clamped before use so that the check is
+// memory-safe on any input.
+__global__ void __launch_bounds__(kBlock) k_validate(int n, int nnz, const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col, int* ctl) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    int bad = 0;
+    for (int v = wave; v < n; v += nwaves) {
+        int b = row_ptr[v], e = row_ptr[v + 1];
+        if (b < 0 || e < b || e > nnz) { bad = 1; continue; }
+        if (v == 0 && b != 0) bad = 1;
+        if (v == n - 1 && e != nnz) bad = 1;
+        for (int j = b + lane; j < e; j += 64) {
+            int w = col[j];
+            if (w < 0 || w >= n || w == v) { bad = 1; continue; }
+            if (j > b && col[j - 1] >= w) bad = 1;
+            int lo = row_ptr[w], hi = row_ptr[w + 1];
+            lo = lo < 0 ? 0 : (lo > nnz ? nnz : lo);
+            hi = hi < lo ? lo : (hi > nnz ? nnz : hi);
+            while (lo < hi) {
+                int mid = lo + ((hi - lo) >> 1);
+                if (col[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            int ehi = row_ptr[w + 1];
+            ehi = ehi > nnz ? nnz : ehi;
+            if (lo >= ehi || col[lo] != v) bad = 1;
+        }
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(&ctl[CTL_ERR], 1);
+}
+
+// --------------------------------------------------------------- keys
+
+__global__ void __launch_bounds__(kBlock) k_degree_key(int n, const int* __restrict__ row_ptr,
+                                                      int* key, int* val, int* ctl) {
+    int mx = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int d = row_ptr[v + 1] - row_ptr[v];
+        key[v] = d;
+        val[v] = v;
+        mx = d > mx ? d : mx;
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) atomicMax(&ctl[CTL_MAXKEY], mx);
+}
+
+// Degeneracy order by level-synchronous peeling (the paper only states that its
+// k-core decomposition runs on the GPU; this schedule is ours).
+//
+// Level c starts when no live vertex has degree <= c - 1; its first frontier is
+// every live vertex of degree <= c.  Each round removes the whole frontier
+// (rnd[v] = round), decrements live neighbours, and a neighbour whose degree
+// falls from c + 1 to c joins the next frontier.  When a round leaves an empty
+// frontier the next level is the minimum live degree.  A vertex removed in round
+// r at level c had at most c live neighbours at the start of round r, and its
+// out-neighbours under the (round, id) order are among them, so the out-degree
+// is bounded by the degeneracy (the largest level).
+__global__ void __launch_bounds__(kBlock) k_peel(int n, const int* __restrict__ row_ptr,
+                                                const int* __restrict__ col, int* deg, int* rnd,
+                                                int* fr0, int* fr1, int* val, int* ctl) {
+    cg::grid_group grid = cg::this_grid();
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nth = gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = tid >> 6;
+    const int nwaves = nth >> 6;
+
+    for (int v = tid; v < n; v += nth) {
+        deg[v] = row_ptr[v + 1] - row_ptr[v];
+        rnd[v] = -1;
+        val[v] = v;
+    }
+    if (tid == 0) {
+        ctl[CTL_SIZE0] = ctl[CTL_SIZE0 + 1] = ctl[CTL_SIZE0 + 2] = 0;
+        ctl[CTL_MIN] = INT_MAX;
+    }
+    grid.sync();
+
+    int removed = 0, r = 0, c = -1, degen = 0;
+    while (removed < n) {
+        int* cur = (r & 1) ? fr1 : fr0;
+        int* nxt = (r & 1) ? fr0 : fr1;
+        int* csize = &ctl[CTL_SIZE0 + r % 3];
+        int* nsize = &ctl[CTL_SIZE0 + (r + 1) % 3];
+        int fsize = ld_acquire(csize);
+        if (fsize == 0) {
+            int mn = INT_MAX;
+            for (int v = tid; v < n; v += nth)
+                if (ld_acquire(&rnd[v]) < 0) {
+                    int d = ld_acquire(&deg[v]);
+                    mn = d < mn ? d : mn;
+                }
+            mn = wave_min(mn);
+            if (lane == 0 && mn != INT_MAX) atomicMin(&ctl[CTL_MIN], mn);
+            grid.sync();
+            c = ld_acquire(&ctl[CTL_MIN]);
+            for (int v = tid; v < n; v += nth)
+                if (ld_acquire(&rnd[v]) < 0 && ld_acquire(&deg[v]) <= c) cur[atomicAdd(csize, 1)] = v;
+            grid.sync();
+            fsize = ld_acquire(csize);
+            if (tid == 0) ctl[CTL_MIN] = INT_MAX;
+            degen = c > degen ? c : degen;
+        }
+        if (tid == 0) ctl[CTL_SIZE0 + (r + 2) % 3] = 0;
+        for (int fi = wave; fi < fsize; fi += nwaves) {
+            int v = ld_acquire(&cur[fi]);
+            if (lane == 0) rnd[v] = r;
+            int b = row_ptr[v], e = row_ptr[v + 1];
+            for (int j = b + lane; j < e; j += 64) {
+                int w = col[j];
+                if (ld_acquire(&rnd[w]) < 0) {
+                    int old = atomicSub(&deg[w], 1);
+                    if (old == c + 1) nxt[atomicAdd(nsize, 1)] = w;
+                }
+            }
+        }
+        removed += fsize;
+        r++;
+        grid.sync();
+    }
+    if (tid == 0) {
+        ctl[CTL_DEGEN] = degen;
+        ctl[CTL_ROUNDS] = r;
+        ctl[CTL_MAXKEY] = r > 0 ? r - 1 : 0;
+    }
+}
+
+// ------------------------------------------------------- block-level scan
+
+// Exclusive scan of one int per thread across the block; returns the block total
+// through *total.  All threads of the block must call it.
+__device__ int block_exclusive_scan(int x, int* total, int* sh /* >= kBlock/64 + 1 */) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i < kBlock / 64; i++) {
+            int t = sh[i];
+            sh[i] = run;
+            run += t;
+        }
+        sh[kBlock / 64] = run;
+    }
+    __syncthreads();
+    int res = inc - x + sh[w];
+    *total = sh[kBlock / 64];
+    __syncthreads();
+    return res;
+}
+
+// --------------------------------------------------------- exclusive scan
+
+// Pass 1: per-tile sums.  mode 0: sum of in[]; mode 1: count of radix zeros.
+__global__ void __launch_bounds__(kBlock) k_tile_sum(int count, const int* __restrict__ in, int bit,
+                                                    int mode, int* tile_sum) {
+    __shared__ int sh[kBlock / 64 + 1];
+    const int base = blockIdx.x * kTile + threadIdx.x * kItems;
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int idx = base + i;
+        if (idx < count) s += mode == 0 ? in[idx] : (((in[idx] >> bit) & 1) == 0);
+    }
+    int tot;
+    block_exclusive_scan(s, &tot, sh);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// Pass 2: exclusive scan of the tile sums by one block; total into *total.
+__global__ void __launch_bounds__(kBlock) k_scan_tiles(int ntiles, int* tile_sum, int* total) {
+    __shared__ int sh[kBlock / 64 + 1];
+    int carry = 0;
+    for (int base = 0; base < ntiles; base += kBlock) {
+        int idx = base + threadIdx.x;
+        int x = idx < ntiles ? tile_sum[idx] : 0;
+        int tot;
+        int ex = block_exclusive_scan(x, &tot, sh);
+        if (idx < ntiles) tile_sum[idx] = ex + carry;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// Pass 3 (mode 0): out[i] = exclusive prefix of in[] (+ tile offset); out[count]
+// = total.
+__global__ void __launch_bounds__(kBlock) k_scan_apply(int count, const int* __restrict__ in,
+                                                      const int* __restrict__ tile_off,
+                                                      const int* __restrict__ total, int* out) {
+    __shared__ int sh[kBlock / 64 + 1];
+    const int base = blockIdx.x * kTile + threadIdx.x * kItems;
+    int v[kItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int idx = base + i;
+        v[i] = idx < count ? in[idx] : 0;
+        s += v[i];
+    }
+    int tot;
+    int run = block_exclusive_scan(s, &tot, sh) + tile_off[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int idx = base + i;
+        if (idx < count) out[idx] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[count] = *total;
+}
+
+// Pass 3 (radix): stable split on `bit`: zeros keep their order at the front,
+// ones keep their order after all zeros.
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(int count, int bit, const int* __restrict__ kin,
+                                                         const int* __restrict__ vin,
+                                                         const int* __restrict__ tile_off,
+                                                         const int* __restrict__ zeros, int* kout,
+                                                         int* vout) {
+    __shared__ int sh[kBlock / 64 + 1];
+    const int base = blockIdx.x * kTile + threadIdx.x * kItems;
+    int k[kItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int idx = base + i;
+        k[i] = idx < count ? kin[idx] : 0;
+        s += idx < count ? (((k[i] >> bit) & 1) == 0) : 0;
+    }
+    int tot;
+    int zb = block_exclusive_scan(s, &tot, sh) + tile_off[blockIdx.x];
+    const int nz = *zeros;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int idx = base + i;
+        if (idx < count) {
+            int one = (k[i] >> bit) & 1;
+            int pos = one ? nz + (idx - zb) : zb;
+            kout[pos] = k[i];
+            vout[pos] = vin[idx];
+            zb += one ? 0 : 1;
+        }
+    }
+}
+
+// --------------------------------------------------------- filter, compact
+
+__global__ void __launch_bounds__(kBlock) k_rank(int n, const int* __restrict__ perm, int* rank) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        rank[perm[i]] = i;
+}
+
+// Out-degree of new vertex i: neighbours of perm[i] with a larger new id.
+__global__ void __launch_bounds__(kBlock) k_outdeg(int n, const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ col, const int* __restrict__ perm,
+                                                  const int* __restrict__ rank, int* outdeg, int* ctl) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    int mx = 0;
+    for (int i = wave; i < n; i += nwaves) {
+        int v = perm[i];
+        int b = row_ptr[v], e = row_ptr[v + 1];
+        int cnt = 0;
+        for (int j = b + lane; j < e; j += 64) cnt += rank[col[j]] > i;
+        cnt = wave_sum(cnt);
+        if (lane == 0) outdeg[i] = cnt;
+        mx = cnt > mx ? cnt : mx;
+    }
+    if (lane == 0) atomicMax(&ctl[CTL_DMAX], mx);
+}
+
+// Gather row i's kept neighbours (as new ids) into LDS, then place each at its
+// rank within the row (count of smaller entries): col[] rows come out sorted.
+// Rows longer than kRowCap go to tmp[] unsorted and are finished by
+// k_sort_long_rows.
+__global__ void __launch_bounds__(kBlock) k_fill(int n, const int* __restrict__ row_ptr,
+                                                const int* __restrict__ col, const int* __restrict__ perm,
+                                                const int* __restrict__ rank,
+                                                const int* __restrict__ dag_ptr, int* dag_col, int* dag_src,
+                                                int* tmp, int* ctl) {
+    __shared__ int rows[kBlock / 64][kRowCap];
+    const int lane = threadIdx.x & 63;
+    const int wslot = threadIdx.x >> 6;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    int* row = rows[wslot];
+    for (int i = wave; i < n; i += nwaves) {
+        const int base = dag_ptr[i];
+        const int len = dag_ptr[i + 1] - base;
+        if (len == 0) continue;
+        const bool in_lds = len <= kRowCap;
+        int* dst = in_lds ? row : tmp + base;
+        int v = perm[i];
+        int b = row_ptr[v], e = row_ptr[v + 1];
+        int pos = 0;
+        for (int j0 = b; j0 < e; j0 += 64) {
+            int j = j0 + lane;
+            int r = j < e ? rank[col[j]] : -1;
+            bool keep = r > i;
+            unsigned long long mask = __ballot(keep);
+            if (keep) dst[pos + __popcll(mask & lanemask_lt())] = r;
+            pos += __popcll(mask);
+        }
+        if (in_lds) {
+            wave_sync_lds();
+            for (int t = lane; t < len; t += 64) {
+                int x = row[t];
+                int below = 0;
+                for (int q = 0; q < len; q++) below += row[q] < x;
+                dag_col[base + below] = x;
+                dag_src[base + below] = i;
+            }
+            wave_sync_lds();
+        } else if (lane == 0) {
+            atomicOr(&ctl[CTL_LONG], 1);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sort_long_rows(int n, const int* __restrict__ dag_ptr,
+                                                          const int* __restrict__ tmp, int* dag_col,
+                                                          int* dag_src) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int i = wave; i < n; i += nwaves) {
+        const int base = dag_ptr[i];
+        const int len = dag_ptr[i + 1] - base;
+        if (len <= kRowCap) continue;
+        const int* row = tmp + base;
+        for (int t = lane; t < len; t += 64) {
+            int x = row[t];
+            int below = 0;
+            for (int q = 0; q < len; q++) below += row[q] < x;
+            dag_col[base + below] = x;
+            dag_src[base + below] = i;
+        }
+    }
+}
+
+struct OrientWs {
+    int *ctl, *key_a, *val_a, *key_b, *val_b, *rank, *outdeg, *tiles, *rnd, *fr0, *fr1, *tmp;
+};
+
+OrientWs carve(void* ws, int n, int nnz, size_t* bytes) {
+    Carver c(ws);
+    OrientWs w;
+    size_t nn = static_cast<size_t>(n > 0 ? n : 1);
+    size_t m = static_cast<size_t>(nnz / 2 > 0 ? nnz / 2 : 1);
+    int ntiles = div_up(static_cast<long long>(n) + 1, kTile) + 1;
+    w.ctl = c.take<int>(CTL_WORDS);
+    w.key_a = c.take<int>(nn);
+    w.val_a = c.take<int>(nn);
+    w.key_b = c.take<int>(nn);
+    w.val_b = c.take<int>(nn);
+    w.rank = c.take<int>(nn);
+    w.outdeg = c.take<int>(nn + 1);
+    w.tiles = c.take<int>(static_cast<size_t>(ntiles));
+    w.rnd = c.take<int>(nn);
+    w.fr0 = c.take<int>(nn);
+    w.fr1 = c.take<int>(nn);
+    w.tmp = c.take<int>(m);
+    *bytes = c.bytes();
+    return w;
+}
+
+int grid_for_waves(long long items_per_wave_units) {
+    long long blocks = (items_per_wave_units + (kBlock / 64) - 1) / (kBlock / 64);
+    long long cap = static_cast<long long>(device_cus()) * 16;
+    if (blocks > cap) blocks = cap;
+    return static_cast<int>(blocks < 1 ? 1 : blocks);
+}
+
+int grid_for_threads(long long n) {
+    long long blocks = (n + kBlock - 1) / kBlock;
+    long long cap = static_cast<long long>(device_cus()) * 16;
+    if (blocks > cap) blocks = cap;
+    return static_cast<int>(blocks < 1 ? 1 : blocks);
+}
+
+// out[0..count] = exclusive prefix sums of in[0..count) with out[count] = total.
+int exclusive_scan(int count, const int* in, int* out, int* tiles, int* total, hipStream_t s) {
+    int ntiles = div_up(count, kTile);
+    if (ntiles < 1) ntiles = 1;
+    k_tile_sum<<<ntiles, kBlock, 0, s>>>(count, in, 0, 0, tiles);
+    k_scan_tiles<<<1, kBlock, 0, s>>>(ntiles, tiles, total);
+    k_scan_apply<<<ntiles, kBlock, 0, s>>>(count, in, tiles, total, out);
+    KC_CHECK(hipGetLastError());
+    return KC_OK;
+}
+
+}  // namespace
+}  // namespace kc
+
+using namespace kc;
+
+extern "C" KC_API size_t kc_orient_workspace(int32_t n, int32_t nnz, int32_t order) {
+    (void)order;
+    if (n < 0 || nnz < 0) return 0;
+    size_t bytes = 0;
+    carve(nullptr, n, nnz, &bytes);
+    return bytes;
+}
+
+extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out, void* ws,
+                                    size_t ws_bytes, int32_t validate, void* stream) {
+    if (!g || !out) return KC_EINVAL;
+    if (order != KC_ORDER_DEGREE && order != KC_ORDER_DEGENERACY) return KC_EINVAL;
+    const int n = g->n, nnz = g->nnz;
+    if (n < 0 || nnz < 0 || (nnz & 1)) return KC_EINVAL;
+    if (!g->row_ptr || !out->row_ptr || (n > 0 && !out->perm)) return KC_EINVAL;
+    if (nnz > 0 && (!g->col || !out->col || !out->src)) return KC_EINVAL;
+    size_t need = 0;
+    OrientWs w = carve(ws, n, nnz, &need);
+    if (!ws || ws_bytes < need) return KC_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int m = nnz / 2;
+
+    out->n = n;
+    out->m = m;
+    out->order = order;
+    out->d_max = 0;
+    out->degeneracy = order == KC_ORDER_DEGENERACY ? 0 : -1;
+    KC_CHECK(hipMemsetAsync(w.ctl, 0, CTL_WORDS * sizeof(int), s));
+    if (n == 0) {
+        if (nnz != 0) return KC_EINVAL;
+        KC_CHECK(hipMemsetAsync(out->row_ptr, 0, sizeof(int), s));
+        KC_CHECK(hipStreamSynchronize(s));
+        return KC_OK;
+    }
+
+    if (validate) {
+        k_validate<<<grid_for_waves(n), kBlock, 0, s>>>(n, nnz, g->row_ptr, g->col, w.ctl);
+        KC_CHECK(hipGetLastError());
+        int err = 0;
+        KC_CHECK(hipMemcpyAsync(&err, w.ctl + CTL_ERR, sizeof(int), hipMemcpyDeviceToHost, s));
+        KC_CHECK(hipStreamSynchronize(s));
+        if (err) return KC_EINVAL;
+    }
+
+    // 1. sort keys
+    if (order == KC_ORDER_DEGREE) {
+        k_degree_key<<<grid_for_threads(n), kBlock, 0, s>>>(n, g->row_ptr, w.key_a, w.val_a, w.ctl);
+        KC_CHECK(hipGetLastError());
+    } else {
+        int occ = 0;
+        KC_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel, kBlock, 0));
+        if (occ < 1) return KC_EDEVICE;
+        int blocks = device_cus() * (occ < 2 ? occ : 2);
+        int n_ = n;
+        const int* rp = g->row_ptr;
+        const int* cl = g->col;
+        int* deg = w.key_b;   // scratch until the sort
+        void* args[] = {&n_, &rp, &cl, &deg, &w.rnd, &w.fr0, &w.fr1, &w.val_a, &w.ctl};
+        KC_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<void*>(k_peel), dim3(blocks), dim3(kBlock),
+                                            args, 0, s));
+        KC_CHECK(hipMemcpyAsync(w.key_a, w.rnd, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+    }
+    int hctl[CTL_WORDS];
+    KC_CHECK(hipMemcpyAsync(hctl, w.ctl, sizeof(hctl), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipStreamSynchronize(s));
+    int bits = 0;
+    while (bits < 31 && (hctl[CTL_MAXKEY] >> bits) != 0) bits++;
+
+    // 2. stable radix sort (key, id) -> position = new id
+    int ntiles = div_up(n, kTile);
+    int *kin = w.key_a, *vin = w.val_a, *kout = w.key_b, *vout = w.val_b;
+    for (int bit = 0; bit < bits; bit++) {
+        k_tile_sum<<<ntiles, kBlock, 0, s>>>(n, kin, bit, 1, w.tiles);
+        k_scan_tiles<<<1, kBlock, 0, s>>>(ntiles, w.tiles, w.ctl + CTL_ZEROS);
+        k_radix_scatter<<<ntiles, kBlock, 0, s>>>(n, bit, kin, vin, w.tiles, w.ctl + CTL_ZEROS, kout, vout);
+        KC_CHECK(hipGetLastError());
+        int* t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+    }
+    KC_CHECK(hipMemcpyAsync(out->perm, vin, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+    k_rank<<<grid_for_threads(n), kBlock, 0, s>>>(n, out->perm, w.rank);
+    KC_CHECK(hipGetLastError());
+
+    // 3. filter: out-degree histogram + exclusive scan -> row_ptr
+    k_outdeg<<<grid_for_waves(n), kBlock, 0, s>>>(n, g->row_ptr, g->col, out->perm, w.rank, w.outdeg, w.ctl);
+    KC_CHECK(hipGetLastError());
+    int st = exclusive_scan(n, w.outdeg, out->row_ptr, w.tiles, w.ctl + CTL_ZEROS, s);
+    if (st != KC_OK) return st;
+
+    // 4. compact + per-row sort
+    if (m > 0) {
+        k_fill<<<grid_for_waves(n), kBlock, 0, s>>>(n, g->row_ptr, g->col, out->perm, w.rank, out->row_ptr,
+                                                   out->col, out->src, w.tmp, w.ctl);
+        KC_CHECK(hipGetLastError());
+    }
+    KC_CHECK(hipMemcpyAsync(hctl, w.ctl, sizeof(hctl), hipMemcpyDeviceToHost, s));
+    int total = 0;
+    KC_CHECK(hipMemcpyAsync(&total, out->row_ptr + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipStreamSynchronize(s));
+    if (hctl[CTL_LONG]) {
+        k_sort_long_rows<<<grid_for_waves(n), kBlock, 0, s>>>(n, out->row_ptr, w.tmp, out->col, out->src);
+        KC_CHECK(hipGetLastError());
+        KC_CHECK(hipStreamSynchronize(s));
+    }
+    if (total != m) return KC_EINVAL;   // not symmetric (only possible without validation)
+    out->d_max = hctl[CTL_DMAX];
+    out->degeneracy = order == KC_ORDER_DEGENERACY ? hctl[CTL_DEGEN] : -1;
+    return KC_OK;
+}

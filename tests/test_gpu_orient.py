@@ -1,0 +1,102 @@
+"""GPU orientation (kc_orient) against the oracle and the DAG invariants."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_dag(kc, g, order):
+    return kc.orient(kc.to_device(g), order)
+
+
+def check_dag(kc, g, d):
+    rp, col, src, perm = kc.dag_to_host(d)
+    assert d.n == g.n and d.m == g.m
+    assert rp[0] == 0 and rp[-1] == g.m
+    assert sorted(perm.tolist()) == list(range(g.n))
+    if g.m:
+        assert np.array_equal(src, np.repeat(np.arange(g.n), np.diff(rp)))
+        assert np.all(col > src), "DAG edges must go from lower to higher new id"
+        same_row = src[1:] == src[:-1]
+        assert np.all(col[1:][same_row] > col[:-1][same_row]), "rows must be strictly increasing"
+        back = np.sort(np.stack([perm[src], perm[col]], axis=1), axis=1)
+        key = back[:, 0].astype(np.int64) * g.n + back[:, 1]
+        e = g.edges()
+        want = e[:, 0].astype(np.int64) * g.n + e[:, 1]
+        assert np.array_equal(np.sort(key), np.sort(want))
+    assert d.d_max == (int(np.diff(rp).max()) if g.n else 0)
+
+
+GRAPHS = [
+    lambda: synth.erdos_renyi(2000, 0.01, 1),
+    lambda: synth.chung_lu(5000, 2.1, 16.0, 400.0, 2),
+    lambda: synth.dense_core(6000, 10.0, 2.1, 5, 20, 40, 0.9, 3),
+    lambda: synth.complete(50),
+    lambda: synth.disjoint_union(synth.cycle(30), synth.empty(5)),
+]
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_degree_order_matches_oracle(kc, gi):
+    g = GRAPHS[gi]()
+    d = gpu_dag(kc, g, kc.ORDER_DEGREE)
+    check_dag(kc, g, d)
+    od = oracle.orient(g, oracle.DEGREE)
+    # degree order is (deg, id): the GPU relabelling equals the oracle's rank order
+    _, _, _, perm = kc.dag_to_host(d)
+    assert np.array_equal(perm, np.argsort(od.rank, kind="stable"))
+    assert d.d_max == od.d_max
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_degeneracy_order(kc, gi):
+    g = GRAPHS[gi]()
+    d = gpu_dag(kc, g, kc.ORDER_DEGENERACY)
+    check_dag(kc, g, d)
+    od = oracle.orient(g, oracle.DEGENERACY)
+    assert d.degeneracy == od.degeneracy          # the degeneracy itself is unique
+    assert d.d_max <= d.degeneracy
+
+
+def test_config_powerlaw_orientation(kc):
+    g = synth.config_powerlaw(wmax=5657.0)
+    for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY):
+        d = gpu_dag(kc, g, order)
+        check_dag(kc, g, d)
+        od = oracle.orient(g, order)
+        if order == kc.ORDER_DEGREE:
+            assert d.d_max == od.d_max
+        else:
+            assert d.degeneracy == od.degeneracy and d.d_max <= d.degeneracy
+
+
+def test_empty_and_tiny(kc):
+    for g in (synth.empty(1), synth.empty(7), synth.complete(2)):
+        for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY):
+            check_dag(kc, g, gpu_dag(kc, g, order))
+
+
+def test_validation_rejects_malformed(kc):
+    import torch
+    g = synth.erdos_renyi(200, 0.05, 4)
+    cases = []
+    c = g.col.copy(); c[0], c[1] = c[1], c[0]; cases.append((g.row_ptr, c))          # unsorted row
+    c = g.col.copy(); c[3] = g.n + 7; cases.append((g.row_ptr, c))                    # id out of range
+    c = g.col.copy(); v = int(np.searchsorted(g.row_ptr, 5, side="right") - 1); c[5] = v; cases.append((g.row_ptr, c))  # self-loop
+    rp = g.row_ptr.copy(); rp[10] = rp[11] + 3; cases.append((rp, g.col))             # non-monotone offsets
+    e = g.edges()[1:]                                                                 # drop one direction of an edge
+    und = synth.from_pairs(g.n, e)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    keep = ~((src == g.edges()[0][0]) & (g.col == g.edges()[0][1]))
+    rp2 = np.concatenate([[0], np.cumsum(np.bincount(src[keep], minlength=g.n))]).astype(np.int32)
+    cases.append((rp2, g.col[keep]))
+    assert und.m == g.m - 1
+    for rp_, col_ in cases:
+        dev = kc.Csr(g.n, torch.as_tensor(np.ascontiguousarray(rp_, np.int32)).cuda(),
+                     torch.as_tensor(np.ascontiguousarray(col_, np.int32)).cuda())
+        with pytest.raises(kc.KcError) as e:
+            kc.orient(dev, kc.ORDER_DEGREE, validate=True)
+        assert e.value.code == kc.EINVAL
