@@ -86,16 +86,37 @@ typedef struct kc_dag {
     int32_t* perm;
 } kc_dag;
 
+/* Optional per-call measurements (host struct filled by kc_count / kc_count_all
+ * when kc_opts.profile is non-NULL).  Times are GPU durations from HIP events
+ * recorded on the call's stream around each phase.  nodes / word_ops are filled
+ * only when kc_opts.collect_stats != 0, which runs a separately compiled,
+ * slower variant of the traversal kernels that counts its work: nodes = search
+ * tree nodes expanded by the traversal (intersections of a candidate set with
+ * one adjacency row), word_ops = sum over those nodes of the root's bitset row
+ * length in 32-bit words. */
+typedef struct kc_profile {
+    float ms_classify;         /* root classification into light / heavy lists */
+    float ms_light;            /* traversal kernel over light roots             */
+    float ms_heavy;            /* traversal kernel over heavy roots             */
+    float ms_total;            /* whole call, first to last kernel              */
+    uint64_t nodes[2];         /* [0] light list, [1] heavy list               */
+    uint64_t word_ops[2];
+    int32_t light_roots;       /* roots in each list (after pruning)            */
+    int32_t heavy_roots;
+} kc_profile;
+
 /* Tuning options; NULL means defaults.  scheme: KC_SCHEME_*; width: lanes per
  * sub-wavefront group (1, 2, 4, 8, 16, 32 or 64; 0 = auto) (Sec. 3.5).
+ * collect_stats and profile: see kc_profile.
  * test_preload: added to the internal accumulator before counting; it exists
  * only so that tests can drive the 64-bit overflow path, and is 0 in normal use. */
 typedef struct kc_opts {
     int32_t scheme;
     int32_t width;
-    int32_t reserved0;
-    int32_t reserved1;
+    int32_t collect_stats;
+    int32_t reserved;
     uint64_t test_preload;
+    kc_profile* profile;
 } kc_opts;
 
 /* Bytes of device workspace kc_orient needs for this input size and order. */

@@ -50,10 +50,18 @@ class _Dag(ctypes.Structure):
                 ("src", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
 
 
+class Profile(ctypes.Structure):
+    """kc_profile: per-phase GPU times (ms) and, with collect_stats, work counters."""
+    _fields_ = [("ms_classify", ctypes.c_float), ("ms_light", ctypes.c_float),
+                ("ms_heavy", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("nodes", ctypes.c_uint64 * 2), ("word_ops", ctypes.c_uint64 * 2),
+                ("light_roots", ctypes.c_int32), ("heavy_roots", ctypes.c_int32)]
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("width", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
-                ("test_preload", ctypes.c_uint64)]
+                ("collect_stats", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("test_preload", ctypes.c_uint64), ("profile", ctypes.POINTER(Profile))]
 
 
 _lib = None
@@ -175,8 +183,12 @@ def orient(g: Csr, order: int = ORDER_DEGREE, validate: bool = True, ws: torch.T
     return out
 
 
-def _opts(scheme: int, width: int, test_preload: int) -> _Opts:
-    return _Opts(scheme, width, 0, 0, test_preload)
+def _opts(scheme: int, width: int, test_preload: int, profile: Profile | None = None,
+          collect_stats: bool = False) -> _Opts:
+    o = _Opts(scheme, width, int(bool(collect_stats)), 0, test_preload, None)
+    if profile is not None:
+        o.profile = ctypes.pointer(profile)
+    return o
 
 
 def count_workspace_bytes(d: Dag, k: int, pivot: bool, scheme: int = 0, width: int = 0) -> int:
@@ -186,11 +198,12 @@ def count_workspace_bytes(d: Dag, k: int, pivot: bool, scheme: int = 0, width: i
 
 
 def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
-                 ws: torch.Tensor | None = None, test_preload: int = 0, stream=None):
+                 ws: torch.Tensor | None = None, test_preload: int = 0, stream=None,
+                 profile: Profile | None = None, collect_stats: bool = False):
     """(status, count) of kc_count without raising."""
     L = lib()
     cd = d._c()
-    o = _opts(scheme, width, test_preload)
+    o = _opts(scheme, width, test_preload, profile, collect_stats)
     need = int(L.kc_count_workspace(ctypes.byref(cd), k, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)
@@ -201,23 +214,25 @@ def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
 
 
 def count(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
-          ws: torch.Tensor | None = None, stream=None) -> int:
+          ws: torch.Tensor | None = None, stream=None, profile: Profile | None = None,
+          collect_stats: bool = False) -> int:
     """Number of k-cliques (kc_count); exact Python int."""
-    st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream)
+    st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream, profile, collect_stats)
     if st != OK:
         raise KcError(st, "kc_count")
     return val
 
 
 def count_all(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = SCHEME_AUTO,
-              width: int = 0, ws: torch.Tensor | None = None, stream=None):
+              width: int = 0, ws: torch.Tensor | None = None, stream=None,
+              profile: Profile | None = None):
     """([c_0, ..., c_cap], omega) for every clique size (kc_count_all)."""
     L = lib()
     if cap is None:
         cap = d.d_max + 2
     cap = max(int(cap), 2)
     cd = d._c()
-    o = _opts(scheme, width, 0)
+    o = _opts(scheme, width, 0, profile)
     need = int(L.kc_count_workspace(ctypes.byref(cd), 0, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)

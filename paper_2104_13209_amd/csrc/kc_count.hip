@@ -53,6 +53,7 @@ struct GoParams {
     const int* __restrict__ nroots;  // device count of this list
     int* head;                       // device queue head of this list
     unsigned long long* acc;         // [lo, hi]
+    unsigned long long* stats;       // [nodes, word_ops] (stats variant only)
     int s_cap;                       // LDS rows per team
     int levels;                      // stack levels per group
 };
@@ -126,8 +127,9 @@ __device__ __forceinline__ void team_sync() {
 // ------------------------------------------------------------- traversal
 
 // G: lanes per group; MAXW: bitset words per row this instantiation handles;
-// TW: wavefronts per team (1 = wave per root, 4 = workgroup per root).
-template <int G, int MAXW, int TW, bool EC>
+// TW: wavefronts per team (1 = wave per root, 4 = workgroup per root);
+// STATS: also count expanded nodes and their bitset words (measurement only).
+template <int G, int MAXW, int TW, bool EC, bool STATS>
 __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
     static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "group size");
     constexpr int WPL = (MAXW + G - 1) / G;             // words per lane
@@ -156,6 +158,7 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
     const int nroots = *P.nroots;
 
     unsigned long long acc = 0;
+    unsigned long long st_nodes = 0, st_words = 0;
 
     for (;;) {
         // ---- fetch a root
@@ -286,6 +289,10 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
             for (int t = 0; t < WPL; t++) mine = (t == tsel) ? R[t] : mine;
             const unsigned int wv = static_cast<unsigned int>(__shfl(static_cast<int>(mine), owner));
             const int v = ((owner - gbase) + tsel * G) * 32 + (__ffs(wv) - 1);
+            if (STATS && glane == 0) {
+                st_nodes += 1;
+                st_words += static_cast<unsigned long long>((s + 31) >> 5);
+            }
             if (lane == owner) {
 #pragma unroll
                 for (int t = 0; t < WPL; t++)
@@ -323,13 +330,21 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
     unsigned long long lo, hi;
     wave_sum_u128(acc, lo, hi);
     if (lane == 0) atomic_add_u128(P.acc, P.acc + 1, lo, hi);
+    if (STATS) {
+        st_nodes = wave_sum(st_nodes);
+        st_words = wave_sum(st_words);
+        if (lane == 0) {
+            atomicAdd(P.stats, st_nodes);
+            atomicAdd(P.stats + 1, st_words);
+        }
+    }
 }
 
 // --------------------------------------------------------------- launch
 
 struct CountWs {
     int* ctl;
-    unsigned long long* acc;
+    unsigned long long* acc;   // [lo, hi, light nodes, light words, heavy nodes, heavy words]
     int* light;
     int* heavy;
 };
@@ -338,7 +353,7 @@ CountWs carve_count(void* ws, int nroots_max, size_t* bytes) {
     Carver c(ws);
     CountWs w;
     w.ctl = c.take<int>(CC_WORDS);
-    w.acc = c.take<unsigned long long>(4);
+    w.acc = c.take<unsigned long long>(8);
     w.light = c.take<int>(static_cast<size_t>(nroots_max > 0 ? nroots_max : 1));
     w.heavy = c.take<int>(static_cast<size_t>(nroots_max > 0 ? nroots_max : 1));
     *bytes = c.bytes();
@@ -352,7 +367,7 @@ int levels_for(int k, bool ec) {
 }
 
 template <int G, int MAXW, int TW, bool EC>
-int launch_go(const GoParams& base, int s_cap, hipStream_t s) {
+int launch_go(const GoParams& base, int s_cap, bool stats, hipStream_t s) {
     constexpr int TEAMS = kWavesPerBlock / TW;
     constexpr int GROUPS = 64 * TW / G;
     GoParams P = base;
@@ -361,7 +376,7 @@ int launch_go(const GoParams& base, int s_cap, hipStream_t s) {
     const TeamLayout L = team_layout(s_cap, MAXW, GROUPS, P.levels);
     const size_t lds_bytes = static_cast<size_t>(L.total) * TEAMS * sizeof(unsigned int);
     if (lds_bytes > 160 * 1024) return KC_EUNSUPPORTED;
-    auto kern = k_go<G, MAXW, TW, EC>;
+    auto kern = stats ? k_go<G, MAXW, TW, EC, true> : k_go<G, MAXW, TW, EC, false>;
     if (lds_bytes > 64 * 1024)
         KC_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)));
@@ -375,34 +390,50 @@ int launch_go(const GoParams& base, int s_cap, hipStream_t s) {
 }
 
 template <bool EC>
-int launch_light(const GoParams& P, int width, hipStream_t s) {
+int launch_light(const GoParams& P, int width, bool st, hipStream_t s) {
     switch (width) {
-        case 1: return launch_go<1, 2, 1, EC>(P, kLightCap, s);
-        case 2: return launch_go<2, 2, 1, EC>(P, kLightCap, s);
-        case 4: return launch_go<4, 2, 1, EC>(P, kLightCap, s);
-        case 8: return launch_go<8, 2, 1, EC>(P, kLightCap, s);
+        case 1: return launch_go<1, 2, 1, EC>(P, kLightCap, st, s);
+        case 2: return launch_go<2, 2, 1, EC>(P, kLightCap, st, s);
+        case 4: return launch_go<4, 2, 1, EC>(P, kLightCap, st, s);
+        case 8: return launch_go<8, 2, 1, EC>(P, kLightCap, st, s);
         default: return KC_EINVAL;
     }
 }
 
 template <bool EC, int MAXW>
-int launch_heavy_w(const GoParams& P, int width, int s_cap, hipStream_t s) {
+int launch_heavy_w(const GoParams& P, int width, int s_cap, bool st, hipStream_t s) {
     switch (width) {
-        case 4: return launch_go<4, MAXW, 4, EC>(P, s_cap, s);
-        case 8: return launch_go<8, MAXW, 4, EC>(P, s_cap, s);
-        case 16: return launch_go<16, MAXW, 4, EC>(P, s_cap, s);
-        case 32: return launch_go<32, MAXW, 4, EC>(P, s_cap, s);
+        case 4: return launch_go<4, MAXW, 4, EC>(P, s_cap, st, s);
+        case 8: return launch_go<8, MAXW, 4, EC>(P, s_cap, st, s);
+        case 16: return launch_go<16, MAXW, 4, EC>(P, s_cap, st, s);
+        case 32: return launch_go<32, MAXW, 4, EC>(P, s_cap, st, s);
         default: return KC_EINVAL;
     }
 }
 
 template <bool EC>
-int launch_heavy(const GoParams& P, int width, int d_max, hipStream_t s) {
+int launch_heavy(const GoParams& P, int width, int d_max, bool st, hipStream_t s) {
     const int s_cap = ((d_max + 31) / 32) * 32;
-    if (d_max <= 128) return launch_heavy_w<EC, 4>(P, width, s_cap, s);
-    if (d_max <= 256) return launch_heavy_w<EC, 8>(P, width, s_cap, s);
-    if (d_max <= 512) return launch_heavy_w<EC, 16>(P, width, s_cap, s);
-    return launch_heavy_w<EC, 32>(P, width, s_cap, s);
+    if (d_max <= 128) return launch_heavy_w<EC, 4>(P, width, s_cap, st, s);
+    if (d_max <= 256) return launch_heavy_w<EC, 8>(P, width, s_cap, st, s);
+    if (d_max <= 512) return launch_heavy_w<EC, 16>(P, width, s_cap, st, s);
+    return launch_heavy_w<EC, 32>(P, width, s_cap, st, s);
+}
+
+// HIP events for kc_profile, created on first use (one set per process).
+struct ProfileEvents {
+    hipEvent_t ev[4];
+    bool ready = false;
+};
+
+int profile_events(ProfileEvents** out) {
+    static ProfileEvents pe;
+    if (!pe.ready) {
+        for (int i = 0; i < 4; i++) KC_CHECK(hipEventCreate(&pe.ev[i]));
+        pe.ready = true;
+    }
+    *out = &pe;
+    return KC_OK;
 }
 
 bool valid_dag(const kc_dag* d) {
@@ -472,8 +503,16 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     const bool ec = scheme == KC_SCHEME_EC;
     const int nroots = ec ? d->m : d->n;
 
+    kc_profile* prof = o ? o->profile : nullptr;
+    const bool stats = o && o->collect_stats;
+    ProfileEvents* pe = nullptr;
+    if (prof) {
+        int st0 = profile_events(&pe);
+        if (st0 != KC_OK) return st0;
+        KC_CHECK(hipEventRecord(pe->ev[0], s));
+    }
     KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
-    unsigned long long init[4] = {preload, 0ull, 0ull, 0ull};
+    unsigned long long init[8] = {preload, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
 
     const int cblocks = div_up(nroots, kBlock) < device_cus() * 8 ? div_up(nroots, kBlock) : device_cus() * 8;
@@ -482,6 +521,7 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     else
         k_classify<false><<<cblocks, kBlock, 0, s>>>(nroots, k, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
     KC_CHECK(hipGetLastError());
+    if (prof) KC_CHECK(hipEventRecord(pe->ev[1], s));
 
     GoParams P;
     P.n = d->n;
@@ -491,27 +531,46 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     P.col = d->col;
     P.src = d->src;
     P.acc = w.acc;
+    P.stats = w.acc + 2;
     P.s_cap = 0;
     P.levels = 0;
 
     P.roots = w.light;
     P.nroots = w.ctl + CC_LIGHT_N;
     P.head = w.ctl + CC_LIGHT_HEAD;
-    int st = ec ? launch_light<true>(P, pick_width(o, d->d_max, true) > 8 ? 8 : pick_width(o, d->d_max, true), s)
-                : launch_light<false>(P, pick_width(o, d->d_max, true) > 8 ? 8 : pick_width(o, d->d_max, true), s);
+    int lw = pick_width(o, d->d_max, true);
+    if (lw > 8) lw = 8;
+    int st = ec ? launch_light<true>(P, lw, stats, s) : launch_light<false>(P, lw, stats, s);
     if (st != KC_OK) return st;
+    if (prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
     if (d->d_max > kLightCap) {
         P.roots = w.heavy;
         P.nroots = w.ctl + CC_HEAVY_N;
         P.head = w.ctl + CC_HEAVY_HEAD;
+        P.stats = w.acc + 4;
         int wd = pick_width(o, d->d_max, false);
         if (wd < 4) wd = 4;
-        st = ec ? launch_heavy<true>(P, wd, d->d_max, s) : launch_heavy<false>(P, wd, d->d_max, s);
+        st = ec ? launch_heavy<true>(P, wd, d->d_max, stats, s) : launch_heavy<false>(P, wd, d->d_max, stats, s);
         if (st != KC_OK) return st;
     }
-    unsigned long long res[2];
+    if (prof) KC_CHECK(hipEventRecord(pe->ev[3], s));
+    unsigned long long res[8];
+    int hctl[CC_WORDS];
     KC_CHECK(hipMemcpyAsync(res, w.acc, sizeof(res), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipMemcpyAsync(hctl, w.ctl, sizeof(hctl), hipMemcpyDeviceToHost, s));
     KC_CHECK(hipStreamSynchronize(s));
+    if (prof) {
+        KC_CHECK(hipEventElapsedTime(&prof->ms_classify, pe->ev[0], pe->ev[1]));
+        KC_CHECK(hipEventElapsedTime(&prof->ms_light, pe->ev[1], pe->ev[2]));
+        KC_CHECK(hipEventElapsedTime(&prof->ms_heavy, pe->ev[2], pe->ev[3]));
+        KC_CHECK(hipEventElapsedTime(&prof->ms_total, pe->ev[0], pe->ev[3]));
+        for (int i = 0; i < 2; i++) {
+            prof->nodes[i] = stats ? res[2 + 2 * i] : 0;
+            prof->word_ops[i] = stats ? res[3 + 2 * i] : 0;
+        }
+        prof->light_roots = hctl[CC_LIGHT_N];
+        prof->heavy_roots = hctl[CC_HEAVY_N];
+    }
     count->lo = res[0];
     count->hi = 0;
     if (res[1] != 0) return KC_EOVERFLOW;
