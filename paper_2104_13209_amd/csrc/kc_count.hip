@@ -26,23 +26,16 @@
 // Every lane keeps its own 64-bit partial count; wavefronts reduce them exactly
 // into a 128-bit device counter when they exit.
 #include <climits>
+#include <new>
 
-#include "kc_internal.h"
+#include "kc_extract.h"
+#include "kc_count_impl.h"
 
 namespace kc {
 namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kLightCap = 64;       // |S| bound of the light list
-
-enum CountCtl {
-    CC_LIGHT_N = 0,    // light root count
-    CC_HEAVY_N = 1,    // heavy root count
-    CC_LIGHT_HEAD = 2, // light queue head
-    CC_HEAVY_HEAD = 3, // heavy queue head
-    CC_WORDS = 8
-};
 
 struct GoParams {
     int n, m, k;
@@ -65,8 +58,6 @@ struct TeamLayout {
     int s_words, b_stride, b_words, stack_words, total;
 };
 
-__host__ __device__ constexpr int b_stride_of(int maxw) { return (maxw > 1 && (maxw % 2) == 0) ? maxw + 1 : maxw; }
-
 __host__ __device__ inline TeamLayout team_layout(int s_cap, int maxw, int groups, int levels) {
     TeamLayout t;
     t.s_words = s_cap;
@@ -79,14 +70,13 @@ __host__ __device__ inline TeamLayout team_layout(int s_cap, int maxw, int group
 
 // ------------------------------------------------------------ classify
 
-// Split roots into light / heavy lists by the bound on |S|; drop roots that
-// cannot contain a k-clique (|S| < k - 1 for VC, < k - 2 for EC).
+// Split roots into light / heavy lists by the bound on |S|; drop roots whose
+// bound is below `need` (a k-clique needs |S| >= k - 1 for VC, >= k - 2 for EC).
 template <bool EC>
-__global__ void __launch_bounds__(kBlock) k_classify(int nroots_total, int k, const int* __restrict__ row_ptr,
+__global__ void __launch_bounds__(kBlock) k_classify(int nroots_total, int need, const int* __restrict__ row_ptr,
                                                     const int* __restrict__ col, const int* __restrict__ src,
                                                     int* light, int* heavy, int* ctl) {
     const int lane = threadIdx.x & 63;
-    const int need = EC ? k - 2 : k - 1;
     for (int base = blockIdx.x * blockDim.x; base < nroots_total; base += gridDim.x * blockDim.x) {
         int r = base + threadIdx.x;
         int bound = -1;
@@ -116,14 +106,6 @@ __global__ void __launch_bounds__(kBlock) k_classify(int nroots_total, int k, co
     }
 }
 
-// ------------------------------------------------------------- team sync
-
-template <int TW>
-__device__ __forceinline__ void team_sync() {
-    if (TW == 1) wave_sync_lds();
-    else __syncthreads();
-}
-
 // ------------------------------------------------------------- traversal
 
 // G: lanes per group; MAXW: bitset words per row this instantiation handles;
@@ -135,7 +117,6 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
     constexpr int WPL = (MAXW + G - 1) / G;             // words per lane
     constexpr int TEAM_LANES = 64 * TW;
     constexpr int GROUPS = TEAM_LANES / G;              // groups per team
-    constexpr int XG = 16;                              // lanes per row during extraction
     extern __shared__ unsigned int lds[];
 
     const int lane = threadIdx.x & 63;
@@ -168,37 +149,8 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
         if (root >= nroots) break;
         const int rid = P.roots[root];
 
-        // ---- candidate set S (sorted)
-        if (!EC) {
-            const int b = P.row_ptr[rid], e = P.row_ptr[rid + 1];
-            for (int j = tl; j < e - b; j += TEAM_LANES) S[j] = P.col[b + j];
-            if (tl == 0) ctl[1] = e - b;
-        } else if (tl < 64) {
-            // one wavefront intersects N+(v) with N+(u) (ordered compaction)
-            const int u = P.src[rid], v = P.col[rid];
-            const int ub = P.row_ptr[u], ue = P.row_ptr[u + 1];
-            const int vb = P.row_ptr[v], ve = P.row_ptr[v + 1];
-            int cnt = 0;
-            for (int j0 = vb; j0 < ve; j0 += 64) {
-                const int j = j0 + lane;
-                bool hit = false;
-                int x = 0;
-                if (j < ve) {
-                    x = P.col[j];
-                    int lo = ub, hi = ue;
-                    while (lo < hi) {
-                        int mid = (lo + hi) >> 1;
-                        if (P.col[mid] < x) lo = mid + 1; else hi = mid;
-                    }
-                    hit = lo < ue && P.col[lo] == x;
-                }
-                unsigned long long mk = __ballot(hit);
-                if (hit) S[cnt + __popcll(mk & lanemask_lt())] = x;
-                cnt += __popcll(mk);
-            }
-            if (lane == 0) ctl[1] = cnt;
-        }
-        team_sync<TW>();
+        // ---- candidate set S (sorted) and bitset rows B[i] (bit j <=> S[j] in N+(S[i]))
+        extract_set<TW, EC>(rid, P.row_ptr, P.col, P.src, tl, S, &ctl[1]);
         const int s = ctl[1];
         if (EC && k == 3) {
             // every vertex of S closes a triangle with the root edge
@@ -206,27 +158,8 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
             team_sync<TW>();
             continue;
         }
-
-        // ---- bitset rows: B[i] bit j  <=>  S[j] in N+(S[i])
-        for (int w = tl; w < s * stride; w += TEAM_LANES) B[w] = 0u;
         if (tl == 0) ctl[0] = 0;
-        team_sync<TW>();
-        const int smax = s > 0 ? S[s - 1] : 0;
-        for (int i = tl / XG; i < s; i += TEAM_LANES / XG) {
-            const int w = S[i];
-            const int b = P.row_ptr[w], e = P.row_ptr[w + 1];
-            for (int j = b + (tl % XG); j < e; j += XG) {
-                const int x = P.col[j];
-                if (x > smax) break;                    // rows are sorted: nothing further is in S
-                int lo = i + 1, hi = s;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if (S[mid] < x) lo = mid + 1; else hi = mid;
-                }
-                if (lo < s && S[lo] == x) atomicOr(&B[i * stride + (lo >> 5)], 1u << (lo & 31));
-            }
-        }
-        team_sync<TW>();
+        extract_rows<TW, false>(s, P.row_ptr, P.col, tl, S, B, stride);
 
         // ---- traversal: groups take subtrees (tasks i = 0..s-1) dynamically
         unsigned int R[WPL];
@@ -342,24 +275,6 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
 
 // --------------------------------------------------------------- launch
 
-struct CountWs {
-    int* ctl;
-    unsigned long long* acc;   // [lo, hi, light nodes, light words, heavy nodes, heavy words]
-    int* light;
-    int* heavy;
-};
-
-CountWs carve_count(void* ws, int nroots_max, size_t* bytes) {
-    Carver c(ws);
-    CountWs w;
-    w.ctl = c.take<int>(CC_WORDS);
-    w.acc = c.take<unsigned long long>(8);
-    w.light = c.take<int>(static_cast<size_t>(nroots_max > 0 ? nroots_max : 1));
-    w.heavy = c.take<int>(static_cast<size_t>(nroots_max > 0 ? nroots_max : 1));
-    *bytes = c.bytes();
-    return w;
-}
-
 int levels_for(int k, bool ec) {
     const int p0 = ec ? 3 : 2;
     int lv = k - 2 - p0;
@@ -458,6 +373,117 @@ int pick_width(const kc_opts* o, int d_max, bool light) {
     return w;
 }
 
+// Classify roots, run the light and heavy kernels of one traversal, and read
+// the results back.  `pivot_all` selects the pivot kernels (-1: graph
+// orientation, 0: pivot with target k, 1: pivot count-all).
+int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const CountWs& w, bool ec,
+              unsigned long long preload, unsigned long long res[8], int hctl[CC_WORDS],
+              unsigned long long* counts_out, int counts_len, hipStream_t s) {
+    kc_profile* prof = o ? o->profile : nullptr;
+    const bool stats = o && o->collect_stats;
+    ProfileEvents* pe = nullptr;
+    if (prof) {
+        int st0 = profile_events(&pe);
+        if (st0 != KC_OK) return st0;
+        KC_CHECK(hipEventRecord(pe->ev[0], s));
+    }
+    const int nroots = ec ? d->m : d->n;
+    KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
+    unsigned long long init[8] = {preload, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
+    if (pivot_all >= 0) {
+        KC_CHECK(hipMemsetAsync(w.counts, 0, 2 * sizeof(unsigned long long) * (w.binom_n + 1), s));
+        int st0 = pivot_binom_table(w, s);
+        if (st0 != KC_OK) return st0;
+    }
+    // roots that cannot reach the target size are dropped (count-all: cliques of
+    // size >= 3 need |S| >= 2 under a vertex root, >= 1 under an edge root)
+    const int need = pivot_all == 1 ? (ec ? 1 : 2) : (ec ? k - 2 : k - 1);
+    int cblocks = div_up(nroots, kBlock);
+    if (cblocks > device_cus() * 8) cblocks = device_cus() * 8;
+    if (cblocks < 1) cblocks = 1;
+    if (ec)
+        k_classify<true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
+    else
+        k_classify<false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
+    KC_CHECK(hipGetLastError());
+    if (prof) KC_CHECK(hipEventRecord(pe->ev[1], s));
+
+    int st = KC_OK;
+    if (pivot_all < 0) {
+        GoParams P;
+        P.n = d->n;
+        P.m = d->m;
+        P.k = k;
+        P.row_ptr = d->row_ptr;
+        P.col = d->col;
+        P.src = d->src;
+        P.acc = w.acc;
+        P.stats = w.acc + 2;
+        P.s_cap = 0;
+        P.levels = 0;
+        P.roots = w.light;
+        P.nroots = w.ctl + CC_LIGHT_N;
+        P.head = w.ctl + CC_LIGHT_HEAD;
+        int lw = pick_width(o, d->d_max, true);
+        if (lw > 8) lw = 8;
+        st = ec ? launch_light<true>(P, lw, stats, s) : launch_light<false>(P, lw, stats, s);
+        if (st != KC_OK) return st;
+        if (prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
+        if (d->d_max > kLightCap) {
+            P.roots = w.heavy;
+            P.nroots = w.ctl + CC_HEAVY_N;
+            P.head = w.ctl + CC_HEAVY_HEAD;
+            P.stats = w.acc + 4;
+            int wd = pick_width(o, d->d_max, false);
+            if (wd < 4) wd = 4;
+            st = ec ? launch_heavy<true>(P, wd, d->d_max, stats, s) : launch_heavy<false>(P, wd, d->d_max, stats, s);
+            if (st != KC_OK) return st;
+        }
+    } else {
+        PivLaunch L;
+        L.k = k;
+        L.all = pivot_all == 1;
+        L.ec = ec;
+        L.stats = stats;
+        L.d_max = d->d_max;
+        L.row_ptr = d->row_ptr;
+        L.col = d->col;
+        L.src = d->src;
+        L.w = w;
+        st = pivot_launch(L, false, s);
+        if (st != KC_OK) return st;
+        if (prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
+        if (d->d_max > kLightCap) {
+            st = pivot_launch(L, true, s);
+            if (st != KC_OK) return st;
+        }
+    }
+    if (prof) {
+        if (d->d_max <= kLightCap) KC_CHECK(hipEventRecord(pe->ev[2], s));
+        KC_CHECK(hipEventRecord(pe->ev[3], s));
+    }
+    KC_CHECK(hipMemcpyAsync(res, w.acc, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipMemcpyAsync(hctl, w.ctl, CC_WORDS * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (counts_out)
+        KC_CHECK(hipMemcpyAsync(counts_out, w.counts, 2 * sizeof(unsigned long long) * counts_len,
+                                hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipStreamSynchronize(s));
+    if (prof) {
+        KC_CHECK(hipEventElapsedTime(&prof->ms_classify, pe->ev[0], pe->ev[1]));
+        KC_CHECK(hipEventElapsedTime(&prof->ms_light, pe->ev[1], pe->ev[2]));
+        KC_CHECK(hipEventElapsedTime(&prof->ms_heavy, pe->ev[2], pe->ev[3]));
+        KC_CHECK(hipEventElapsedTime(&prof->ms_total, pe->ev[0], pe->ev[3]));
+        for (int i = 0; i < 2; i++) {
+            prof->nodes[i] = stats ? res[2 + 2 * i] : 0;
+            prof->word_ops[i] = stats ? res[3 + 2 * i] : 0;
+        }
+        prof->light_roots = hctl[CC_LIGHT_N];
+        prof->heavy_roots = hctl[CC_HEAVY_N];
+    }
+    return KC_OK;
+}
+
 }  // namespace
 }  // namespace kc
 
@@ -465,12 +491,10 @@ using namespace kc;
 
 extern "C" KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t pivot, const kc_opts* o) {
     (void)k;
-    (void)pivot;
     (void)o;
-    if (!d) return 0;
+    if (!d || d->n < 0 || d->m < 0 || d->d_max < 0) return 0;
     size_t bytes = 0;
-    const int nr = d->m > d->n ? d->m : d->n;
-    carve_count(nullptr, nr, &bytes);
+    carve_count(nullptr, d, pivot != 0, &bytes);
     return bytes;
 }
 
@@ -487,11 +511,9 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
         if (!pivot && count->hi) { count->hi = 0; return KC_EOVERFLOW; }
         return KC_OK;
     }
-    if (pivot) return KC_EUNSUPPORTED;
     if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
     size_t need = 0;
-    const int nr_max = d->m > d->n ? d->m : d->n;
-    CountWs w = carve_count(ws, nr_max, &need);
+    CountWs w = carve_count(ws, d, pivot != 0, &need);
     if (!ws || ws_bytes < need) return KC_ENOMEM;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (k > d->d_max + 1 || d->m == 0) {
@@ -500,86 +522,55 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     }
     const int scheme = pick_scheme(o, k);
     if (scheme != KC_SCHEME_VC && scheme != KC_SCHEME_EC) return KC_EINVAL;
-    const bool ec = scheme == KC_SCHEME_EC;
-    const int nroots = ec ? d->m : d->n;
-
-    kc_profile* prof = o ? o->profile : nullptr;
-    const bool stats = o && o->collect_stats;
-    ProfileEvents* pe = nullptr;
-    if (prof) {
-        int st0 = profile_events(&pe);
-        if (st0 != KC_OK) return st0;
-        KC_CHECK(hipEventRecord(pe->ev[0], s));
-    }
-    KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
-    unsigned long long init[8] = {preload, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
-    KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
-
-    const int cblocks = div_up(nroots, kBlock) < device_cus() * 8 ? div_up(nroots, kBlock) : device_cus() * 8;
-    if (ec)
-        k_classify<true><<<cblocks, kBlock, 0, s>>>(nroots, k, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
-    else
-        k_classify<false><<<cblocks, kBlock, 0, s>>>(nroots, k, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
-    KC_CHECK(hipGetLastError());
-    if (prof) KC_CHECK(hipEventRecord(pe->ev[1], s));
-
-    GoParams P;
-    P.n = d->n;
-    P.m = d->m;
-    P.k = k;
-    P.row_ptr = d->row_ptr;
-    P.col = d->col;
-    P.src = d->src;
-    P.acc = w.acc;
-    P.stats = w.acc + 2;
-    P.s_cap = 0;
-    P.levels = 0;
-
-    P.roots = w.light;
-    P.nroots = w.ctl + CC_LIGHT_N;
-    P.head = w.ctl + CC_LIGHT_HEAD;
-    int lw = pick_width(o, d->d_max, true);
-    if (lw > 8) lw = 8;
-    int st = ec ? launch_light<true>(P, lw, stats, s) : launch_light<false>(P, lw, stats, s);
-    if (st != KC_OK) return st;
-    if (prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
-    if (d->d_max > kLightCap) {
-        P.roots = w.heavy;
-        P.nroots = w.ctl + CC_HEAVY_N;
-        P.head = w.ctl + CC_HEAVY_HEAD;
-        P.stats = w.acc + 4;
-        int wd = pick_width(o, d->d_max, false);
-        if (wd < 4) wd = 4;
-        st = ec ? launch_heavy<true>(P, wd, d->d_max, stats, s) : launch_heavy<false>(P, wd, d->d_max, stats, s);
-        if (st != KC_OK) return st;
-    }
-    if (prof) KC_CHECK(hipEventRecord(pe->ev[3], s));
     unsigned long long res[8];
     int hctl[CC_WORDS];
-    KC_CHECK(hipMemcpyAsync(res, w.acc, sizeof(res), hipMemcpyDeviceToHost, s));
-    KC_CHECK(hipMemcpyAsync(hctl, w.ctl, sizeof(hctl), hipMemcpyDeviceToHost, s));
-    KC_CHECK(hipStreamSynchronize(s));
-    if (prof) {
-        KC_CHECK(hipEventElapsedTime(&prof->ms_classify, pe->ev[0], pe->ev[1]));
-        KC_CHECK(hipEventElapsedTime(&prof->ms_light, pe->ev[1], pe->ev[2]));
-        KC_CHECK(hipEventElapsedTime(&prof->ms_heavy, pe->ev[2], pe->ev[3]));
-        KC_CHECK(hipEventElapsedTime(&prof->ms_total, pe->ev[0], pe->ev[3]));
-        for (int i = 0; i < 2; i++) {
-            prof->nodes[i] = stats ? res[2 + 2 * i] : 0;
-            prof->word_ops[i] = stats ? res[3 + 2 * i] : 0;
-        }
-        prof->light_roots = hctl[CC_LIGHT_N];
-        prof->heavy_roots = hctl[CC_HEAVY_N];
-    }
+    int st = run_count(d, k, pivot ? 0 : -1, o, w, scheme == KC_SCHEME_EC, preload, res, hctl, nullptr, 0, s);
+    if (st != KC_OK) return st;
     count->lo = res[0];
-    count->hi = 0;
-    if (res[1] != 0) return KC_EOVERFLOW;
+    count->hi = pivot ? res[1] : 0ull;
+    if (pivot && (hctl[CC_FLAGS] & 1)) return KC_EOVERFLOW;
+    if (!pivot && res[1] != 0) return KC_EOVERFLOW;
     return KC_OK;
 }
 
 extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,
                                        int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
                                        void* stream) {
-    (void)d; (void)pivot; (void)counts; (void)cap; (void)omega; (void)ws; (void)ws_bytes; (void)o; (void)stream;
-    return KC_EUNSUPPORTED;
+    if (!valid_dag(d) || !counts || !omega || cap < 2) return KC_EINVAL;
+    if (!pivot) return KC_EUNSUPPORTED;
+    if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    size_t need = 0;
+    CountWs w = carve_count(ws, d, true, &need);
+    if (!ws || ws_bytes < need) return KC_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int j = 0; j <= cap; j++) counts[j].lo = counts[j].hi = 0;
+    int om = d->n > 0 ? 1 : 0;
+    bool ovf = false;
+    if (d->m > 0 && d->d_max >= 2) {
+        const int scheme = o && o->scheme == KC_SCHEME_EC ? KC_SCHEME_EC : KC_SCHEME_VC;
+        const int len = w.binom_n + 1;
+        unsigned long long* host = new (std::nothrow) unsigned long long[2 * static_cast<size_t>(len)];
+        if (!host) return KC_ENOMEM;
+        unsigned long long res[8];
+        int hctl[CC_WORDS];
+        int st = run_count(d, 0, 1, o, w, scheme == KC_SCHEME_EC, 0ull, res, hctl, host, len, s);
+        if (st != KC_OK) { delete[] host; return st; }
+        ovf = (hctl[CC_FLAGS] & 1) != 0;
+        for (int j = 3; j < len; j++) {
+            if (host[2 * j] | host[2 * j + 1]) {
+                om = j;
+                if (j <= cap) {
+                    counts[j].lo = host[2 * j];
+                    counts[j].hi = host[2 * j + 1];
+                }
+            }
+        }
+        delete[] host;
+    }
+    counts[0].lo = 1;
+    counts[1].lo = static_cast<unsigned long long>(d->n);
+    counts[2].lo = static_cast<unsigned long long>(d->m);
+    if (d->m > 0 && om < 2) om = 2;
+    *omega = om;
+    return ovf ? KC_EOVERFLOW : KC_OK;
 }

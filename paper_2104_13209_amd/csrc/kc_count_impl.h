@@ -1,0 +1,92 @@
+// Host-side layout shared by the counting sources (not part of the ABI).
+#pragma once
+
+#include "kc_internal.h"
+
+namespace kc {
+
+constexpr int kLightCap = 64;          // |S| bound of the light root list
+constexpr int kPivBlocksPerCU = 8;     // grid cap of the heavy pivot kernel (sizes its stacks)
+
+enum CountCtl {
+    CC_LIGHT_N = 0,      // light root count
+    CC_HEAVY_N = 1,      // heavy root count
+    CC_LIGHT_HEAD = 2,   // light queue head
+    CC_HEAVY_HEAD = 3,   // heavy queue head
+    CC_FLAGS = 4,        // bit 0: a binomial beyond 128 bits was used
+    CC_WORDS = 8
+};
+
+__host__ __device__ constexpr int b_stride_of(int maxw) { return (maxw > 1 && (maxw % 2) == 0) ? maxw + 1 : maxw; }
+
+// Bitset words per row used for a DAG of this d_max (rows of at most 32 * maxw bits).
+inline int maxw_for(int d_max) {
+    if (d_max <= 64) return 2;
+    if (d_max <= 128) return 4;
+    if (d_max <= 256) return 8;
+    if (d_max <= 512) return 16;
+    return 32;
+}
+
+inline int s_cap_for(int d_max) { return ((d_max + 31) / 32) * 32 > kLightCap ? ((d_max + 31) / 32) * 32 : kLightCap; }
+
+// Words of one pivot stack level: I, P_orig, P_remaining (maxw each) + p, np, nh, pad.
+inline int piv_level_words(int maxw) { return 3 * maxw + 4; }
+
+struct CountWs {
+    int* ctl;
+    unsigned long long* acc;      // [lo, hi, light nodes, light words, heavy nodes, heavy words]
+    int* light;
+    int* heavy;
+    unsigned long long* counts;   // count_all: (binom_n + 1) x {lo, hi}
+    unsigned long long* binom;    // (binom_n + 1)^2 x {lo, hi}: C(i, j) at [i * (binom_n + 1) + j]
+    unsigned char* big;           // same shape: 1 if C(i, j) needs more than 128 bits
+    unsigned int* gstack;         // heavy pivot stacks, one slab per resident wavefront
+    int binom_n;
+    size_t slab_words;
+    int slabs;
+};
+
+inline CountWs carve_count(void* ws, const kc_dag* d, bool pivot, size_t* bytes) {
+    Carver c(ws);
+    CountWs w{};
+    const int nr = d->m > d->n ? d->m : d->n;
+    w.ctl = c.take<int>(CC_WORDS);
+    w.acc = c.take<unsigned long long>(8);
+    w.light = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
+    w.heavy = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
+    if (pivot) {
+        const int s_cap = s_cap_for(d->d_max);
+        w.binom_n = s_cap + 2;
+        const size_t cells = static_cast<size_t>(w.binom_n + 1) * (w.binom_n + 1);
+        w.counts = c.take<unsigned long long>(2 * static_cast<size_t>(w.binom_n + 1));
+        w.binom = c.take<unsigned long long>(2 * cells);
+        w.big = c.take<unsigned char>(cells);
+        if (d->d_max > kLightCap) {
+            const int maxw = maxw_for(d->d_max);
+            w.slab_words = static_cast<size_t>(s_cap + 2) * piv_level_words(maxw);
+            w.slabs = device_cus() * kPivBlocksPerCU * 4;
+            w.gstack = c.take<unsigned int>(w.slab_words * w.slabs);
+        }
+    }
+    *bytes = c.bytes();
+    return w;
+}
+
+// Launch description for the pivot kernels (kc_pivot.hip).
+struct PivLaunch {
+    int k;                // clique size (ignored when all)
+    bool all;             // count every size
+    bool ec;              // edge roots
+    bool stats;
+    int d_max;
+    const int* row_ptr;
+    const int* col;
+    const int* src;
+    CountWs w;
+};
+
+int pivot_binom_table(const CountWs& w, hipStream_t s);
+int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s);
+
+}  // namespace kc

@@ -48,13 +48,23 @@ __device__ __forceinline__ T ld_acquire(const T* p) {
 
 // Exact unsigned 128-bit accumulation into device memory: lo receives x and a
 // carry out of lo goes to hi (both 64-bit atomics, so the sum is exact).
-__device__ __forceinline__ void atomic_add_u128(unsigned long long* lo, unsigned long long* hi,
+// Returns true when the 128-bit total wrapped past 2^128.
+__device__ __forceinline__ bool atomic_add_u128(unsigned long long* lo, unsigned long long* hi,
                                                 unsigned long long x_lo, unsigned long long x_hi) {
+    bool carry_in = false;
     if (x_lo) {
         unsigned long long old = atomicAdd(lo, x_lo);
-        if (old + x_lo < old) x_hi += 1;
+        if (old + x_lo < old) {
+            carry_in = true;
+        }
     }
-    if (x_hi) atomicAdd(hi, x_hi);
+    unsigned long long add_hi = x_hi + (carry_in ? 1ull : 0ull);
+    bool wrap = carry_in && add_hi == 0ull;   // x_hi was all ones
+    if (add_hi) {
+        unsigned long long old = atomicAdd(hi, add_hi);
+        wrap |= old + add_hi < old;
+    }
+    return wrap;
 }
 
 // Wave-wide sum of a per-lane u64 into (lo, hi): exact, with carry detection.

@@ -1,0 +1,380 @@
+// Pivoting traversal (paper Sec. 2.3 Fig. 3, hybrid form of Sec. 2.3 / 2.4) for
+// gfx950 wave64, and the exact binomial table its leaves use.
+//
+// Hybrid: the root level is oriented (a vertex root u with S = N+(u), or an edge
+// root u->v with S = N+(u) cap N+(v)); below it the search pivots on the
+// undirected sub-graph induced by S, encoded as bitset rows A[i] (Sec. 3.4).
+// The root vertices are holds.
+//
+// One wavefront walks one root's tree depth-first (the paper keeps a whole block
+// on one tree and splits the pivot search across groups, Sec. 3.2; here the
+// wavefront is that block and its 64 lanes are groups of one lane).  At a node
+// with candidate set I:
+//   pivot   p = argmax over u in I of |I cap A[u]|, ties to the lowest index:
+//           the members of I are compacted with a ballot, lanes score them in
+//           parallel, a wave max-reduction picks the winner;
+//   prune   P = I - A[p] (p stays in P);
+//   branch  for each v in P in increasing order: a child with one more pivot
+//           (v == p) or hold (v != p); with a target k a child with more than k
+//           holds is skipped (the stopping criterion); the child's candidates are
+//           I' = I cap A[v] minus the members of P before v;
+//   leaf    I' empty: with nh holds and np pivots, count mode adds C(np, k - nh);
+//           count-all mode adds C(np, j) to counts[nh + j] for j = 0..np.
+// All control flow is wave-uniform; lane w holds word w of I, P and P-remaining.
+// The explicit stack lives in LDS for light roots (|S| <= 64) and in a per-
+// wavefront global-memory slab for heavy roots (its depth can reach |S|).
+#include "kc_count_impl.h"
+#include "kc_extract.h"
+
+namespace kc {
+namespace {
+
+struct PivParams {
+    int k;
+    int s_cap;
+    int binom_n;
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ col;
+    const int* __restrict__ src;
+    const int* __restrict__ roots;
+    const int* __restrict__ nroots;
+    int* head;
+    int* flags;
+    unsigned long long* acc;                 // [lo, hi]
+    unsigned long long* counts;              // count-all: {lo, hi} per size
+    const unsigned long long* __restrict__ binom;
+    const unsigned char* __restrict__ big;
+    unsigned int* gstack;
+    size_t slab_words;
+    unsigned long long* stats;               // [nodes, words]
+};
+
+// ------------------------------------------------------------ binomials
+
+// 128-bit value as four 32-bit limbs, little endian.
+struct U4 { unsigned int l[4]; };
+
+// x * m / d exactly, where d divides x * m; false when the result needs more
+// than 128 bits.  The product is formed in five limbs so that no intermediate
+// overflow is mistaken for an oversized result.
+__device__ bool muldiv(U4& x, unsigned int m, unsigned int d) {
+    unsigned int p[5];
+    unsigned long long carry = 0;
+    for (int i = 0; i < 4; i++) {
+        unsigned long long t = static_cast<unsigned long long>(x.l[i]) * m + carry;
+        p[i] = static_cast<unsigned int>(t);
+        carry = t >> 32;
+    }
+    p[4] = static_cast<unsigned int>(carry);
+    unsigned long long r = 0;
+    for (int i = 4; i >= 0; i--) {
+        unsigned long long cur = (r << 32) | p[i];
+        p[i] = static_cast<unsigned int>(cur / d);
+        r = cur % d;
+    }
+    for (int i = 0; i < 4; i++) x.l[i] = p[i];
+    return p[4] == 0;
+}
+
+// Row i of Pascal's triangle per thread: C(i, j) for j <= i / 2 from
+// C(i, j + 1) = C(i, j) (i - j) / (j + 1), mirrored for j > i / 2.  Entries past
+// 128 bits are flagged in big[] (and so is every later one on the rising half).
+__global__ void k_binom(int N, unsigned long long* tab, unsigned char* big) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > N) return;
+    const size_t row = static_cast<size_t>(i) * (N + 1);
+    U4 c = {{1u, 0u, 0u, 0u}};
+    bool ok = true;
+    for (int j = 0; j <= i / 2; j++) {
+        const unsigned long long lo = c.l[0] | (static_cast<unsigned long long>(c.l[1]) << 32);
+        const unsigned long long hi = c.l[2] | (static_cast<unsigned long long>(c.l[3]) << 32);
+        for (int side = 0; side < 2; side++) {
+            const int jj = side ? i - j : j;
+            tab[2 * (row + jj)] = ok ? lo : ~0ull;
+            tab[2 * (row + jj) + 1] = ok ? hi : ~0ull;
+            big[row + jj] = ok ? 0 : 1;
+        }
+        if (ok && j + 1 <= i / 2) ok = muldiv(c, static_cast<unsigned int>(i - j), static_cast<unsigned int>(j + 1));
+    }
+    for (int j = i + 1; j <= N; j++) {
+        tab[2 * (row + j)] = 0;
+        tab[2 * (row + j) + 1] = 0;
+        big[row + j] = 0;
+    }
+}
+
+// ------------------------------------------------------------- traversal
+
+__device__ __forceinline__ unsigned int rdlane(unsigned int v, int l) {
+    return static_cast<unsigned int>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+}
+
+// (lo, hi) += (xlo, xhi); sets ovf when the sum wraps past 2^128.
+__device__ __forceinline__ void add_u128(unsigned long long& lo, unsigned long long& hi, unsigned long long xlo,
+                                         unsigned long long xhi, int& ovf) {
+    const unsigned long long s = lo + xlo;
+    const unsigned long long c = s < lo ? 1ull : 0ull;
+    const unsigned long long t = hi + xhi;
+    const unsigned long long u = t + c;
+    ovf |= (t < hi || u < t) ? 1 : 0;
+    hi = u;
+    lo = s;
+}
+
+// Stack reload: a global-memory slab is read with device-coherent loads so that a
+// line cached in the (non-coherent) vector L1 by an earlier pop of the same level
+// cannot return stale words.
+template <bool G>
+__device__ __forceinline__ unsigned int st_load(const unsigned int* p) {
+    if (G) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+
+// MAXW: bitset words per row; EC: edge roots; ALL: count every size;
+// GST: stack in global memory; WPB: wavefronts per block (each its own team).
+template <int MAXW, bool EC, bool ALL, bool GST, int WPB, bool STATS>
+__global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
+    constexpr int LV = 3 * MAXW + 4;
+    extern __shared__ unsigned int lds[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int s_cap = P.s_cap;
+    const int stride = b_stride_of(MAXW);
+    const int cap = s_cap + 2;                        // largest clique size index
+    const int words = 8 + s_cap + s_cap * stride + (ALL ? 4 * (cap + 1) : 0) +
+                      (GST ? 0 : (s_cap + 2) * LV);
+    unsigned int* base = lds + wv * words;
+    int* ctl = reinterpret_cast<int*>(base);
+    int* S = reinterpret_cast<int*>(base + 8);        // candidate set, then member list
+    unsigned int* A = base + 8 + s_cap;
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(A + s_cap * stride);
+    unsigned int* stk = GST ? P.gstack + static_cast<size_t>(blockIdx.x * WPB + wv) * P.slab_words
+                            : A + s_cap * stride + (ALL ? 4 * (cap + 1) : 0);
+    const int k = P.k;
+    const int N1 = P.binom_n + 1;
+    const int nroots = *P.nroots;
+    const int nh_root = EC ? 2 : 1;
+
+    if (ALL)
+        for (int i = lane; i < 2 * (cap + 1); i += 64) cnt[i] = 0ull;
+    unsigned long long acc_lo = 0, acc_hi = 0, nodes = 0, words_done = 0;
+    int ovf = 0;
+
+    // leaf with nh holds and np pivots
+    auto leaf = [&](int np, int nh) {
+        if (!ALL) {
+            if (lane == 0 && nh <= k && nh + np >= k) {
+                const size_t ix = static_cast<size_t>(np) * N1 + (k - nh);
+                ovf |= P.big[ix];
+                add_u128(acc_lo, acc_hi, P.binom[2 * ix], P.binom[2 * ix + 1], ovf);
+            }
+        } else {
+            for (int j = lane; j <= np; j += 64) {
+                const size_t ix = static_cast<size_t>(np) * N1 + j;
+                ovf |= P.big[ix];
+                unsigned long long lo = cnt[2 * (nh + j)], hi = cnt[2 * (nh + j) + 1];
+                add_u128(lo, hi, P.binom[2 * ix], P.binom[2 * ix + 1], ovf);
+                cnt[2 * (nh + j)] = lo;
+                cnt[2 * (nh + j) + 1] = hi;
+            }
+            wave_sync_lds();   // the next leaf may update these slots from other lanes
+        }
+    };
+
+    for (;;) {
+        int root = 0;
+        if (lane == 0) root = atomicAdd(P.head, 1);
+        root = __shfl(root, 0);
+        if (root >= nroots) break;
+        const int rid = P.roots[root];
+        extract_set<1, EC>(rid, P.row_ptr, P.col, P.src, lane, S, &ctl[1]);
+        const int s = ctl[1];
+        extract_rows<1, true>(s, P.row_ptr, P.col, lane, S, A, stride);
+        if (s == 0) {
+            leaf(0, nh_root);
+            wave_sync_lds();
+            continue;
+        }
+        const int W = (s + 31) >> 5;
+
+        unsigned int I = 0, Po = 0, Pr = 0;
+        if (lane < W) I = (lane < W - 1 || (s & 31) == 0) ? ~0u : ((1u << (s & 31)) - 1u);
+        int np = 0, nh = nh_root, level = 0, p = 0;
+
+        // choose the pivot of the node with candidates I; sets p, Po, Pr
+        auto enter = [&]() {
+            int m = 0;
+            for (int c = 0; 2 * c < W; c++) {
+                const unsigned int lo = rdlane(I, 2 * c);
+                const unsigned int hi = 2 * c + 1 < W ? rdlane(I, 2 * c + 1) : 0u;
+                const bool mine = lane < 32 ? ((lo >> lane) & 1u) : ((hi >> (lane - 32)) & 1u);
+                const unsigned long long b = __ballot(mine);
+                if (mine) S[m + __popcll(b & lanemask_lt())] = 64 * c + lane;
+                m += __popcll(b);
+            }
+            wave_sync_lds();
+            unsigned int best = 0;
+            for (int b0 = 0; b0 < m; b0 += 64) {
+                if (b0 + lane < m) {
+                    const int u = S[b0 + lane];
+                    unsigned int sc = 0;
+                    for (int w = 0; w < W; w++) sc += __popc(rdlane(I, w) & A[u * stride + w]);
+                    const unsigned int key = (sc << 16) | (0xffffu - static_cast<unsigned int>(u));
+                    best = key > best ? key : best;
+                }
+            }
+            best = wave_max(best);
+            p = static_cast<int>(0xffffu - (best & 0xffffu));
+            Po = lane < W ? (I & ~A[p * stride + lane]) : 0u;
+            Pr = Po;
+            wave_sync_lds();
+        };
+
+        enter();
+        for (;;) {
+            const unsigned long long bal = __ballot(Pr != 0u);
+            if (bal == 0ull) {
+                if (level == 0) break;
+                level--;
+                unsigned int* f = stk + static_cast<size_t>(level) * LV;
+                if (lane < MAXW) {
+                    I = st_load<GST>(f + lane);
+                    Po = st_load<GST>(f + MAXW + lane);
+                    Pr = st_load<GST>(f + 2 * MAXW + lane);
+                }
+                p = static_cast<int>(st_load<GST>(f + 3 * MAXW));
+                np = static_cast<int>(st_load<GST>(f + 3 * MAXW + 1));
+                nh = static_cast<int>(st_load<GST>(f + 3 * MAXW + 2));
+                continue;
+            }
+            const int w0 = __ffsll(static_cast<long long>(bal)) - 1;
+            const unsigned int word = rdlane(Pr, w0);
+            const int v = 32 * w0 + __ffs(word) - 1;
+            if (lane == w0) Pr &= Pr - 1u;
+            const int np2 = np + (v == p ? 1 : 0);
+            const int nh2 = nh + (v != p ? 1 : 0);
+            if (!ALL && nh2 > k) continue;                  // stopping criterion: holds <= k
+            const unsigned int Ip = lane < W ? (I & A[v * stride + lane] & ~(Po & ~Pr)) : 0u;
+            if (STATS) {
+                nodes += 1;
+                words_done += static_cast<unsigned long long>(W);
+            }
+            if (__ballot(Ip != 0u) != 0ull) {
+                unsigned int* f = stk + static_cast<size_t>(level) * LV;
+                if (lane < MAXW) {
+                    f[lane] = I;
+                    f[MAXW + lane] = Po;
+                    f[2 * MAXW + lane] = Pr;
+                }
+                if (lane == 0) {
+                    f[3 * MAXW] = static_cast<unsigned int>(p);
+                    f[3 * MAXW + 1] = static_cast<unsigned int>(np);
+                    f[3 * MAXW + 2] = static_cast<unsigned int>(nh);
+                }
+                level++;
+                I = Ip;
+                np = np2;
+                nh = nh2;
+                enter();
+            } else {
+                leaf(np2, nh2);
+            }
+        }
+        wave_sync_lds();
+    }
+
+    // flush
+    if (!ALL) {
+        if (lane == 0 && atomic_add_u128(P.acc, P.acc + 1, acc_lo, acc_hi)) ovf = 1;
+    } else {
+        wave_sync_lds();
+        for (int i = lane; i <= cap; i += 64) {
+            const unsigned long long lo = cnt[2 * i], hi = cnt[2 * i + 1];
+            if ((lo | hi) && atomic_add_u128(P.counts + 2 * i, P.counts + 2 * i + 1, lo, hi)) ovf = 1;
+        }
+    }
+    if (__ballot(ovf != 0) != 0ull && lane == 0) atomicOr(P.flags, 1);
+    if (STATS && lane == 0) {
+        atomicAdd(P.stats, nodes);
+        atomicAdd(P.stats + 1, words_done);
+    }
+}
+
+template <int MAXW, bool EC, bool ALL, bool GST, int WPB>
+int launch_piv_t(PivParams P, bool stats, int grid_cap_per_cu, hipStream_t s) {
+    constexpr int LV = 3 * MAXW + 4;
+    const int s_cap = P.s_cap;
+    const int cap = s_cap + 2;
+    const int words = 8 + s_cap + s_cap * b_stride_of(MAXW) + (ALL ? 4 * (cap + 1) : 0) +
+                      (GST ? 0 : (s_cap + 2) * LV);
+    const size_t lds_bytes = static_cast<size_t>(words) * WPB * sizeof(unsigned int);
+    if (lds_bytes > 160 * 1024) return KC_EUNSUPPORTED;
+    auto kern = stats ? k_piv<MAXW, EC, ALL, GST, WPB, true> : k_piv<MAXW, EC, ALL, GST, WPB, false>;
+    if (lds_bytes > 64 * 1024)
+        KC_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)));
+    int occ = 0;
+    KC_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * WPB, lds_bytes));
+    if (occ < 1) return KC_EUNSUPPORTED;
+    if (occ > grid_cap_per_cu) occ = grid_cap_per_cu;
+    kern<<<device_cus() * occ, 64 * WPB, lds_bytes, s>>>(P);
+    KC_CHECK(hipGetLastError());
+    return KC_OK;
+}
+
+template <int MAXW, bool GST, int WPB>
+int launch_piv_m(const PivParams& P, bool ec, bool all, bool stats, int cap, hipStream_t s) {
+    if (ec) {
+        return all ? launch_piv_t<MAXW, true, true, GST, WPB>(P, stats, cap, s)
+                   : launch_piv_t<MAXW, true, false, GST, WPB>(P, stats, cap, s);
+    }
+    return all ? launch_piv_t<MAXW, false, true, GST, WPB>(P, stats, cap, s)
+               : launch_piv_t<MAXW, false, false, GST, WPB>(P, stats, cap, s);
+}
+
+}  // namespace
+
+int pivot_binom_table(const CountWs& w, hipStream_t s) {
+    const int N = w.binom_n;
+    k_binom<<<div_up(N + 1, 64), 64, 0, s>>>(N, w.binom, w.big);
+    KC_CHECK(hipGetLastError());
+    return KC_OK;
+}
+
+int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
+    PivParams P;
+    P.k = L.k;
+    P.binom_n = L.w.binom_n;
+    P.row_ptr = L.row_ptr;
+    P.col = L.col;
+    P.src = L.src;
+    P.flags = L.w.ctl + CC_FLAGS;
+    P.acc = L.w.acc;
+    P.counts = L.w.counts;
+    P.binom = L.w.binom;
+    P.big = L.w.big;
+    P.gstack = L.w.gstack;
+    P.slab_words = L.w.slab_words;
+    if (!heavy) {
+        P.s_cap = kLightCap;
+        P.roots = L.w.light;
+        P.nroots = L.w.ctl + CC_LIGHT_N;
+        P.head = L.w.ctl + CC_LIGHT_HEAD;
+        P.stats = L.w.acc + 2;
+        return launch_piv_m<2, false, 4>(P, L.ec, L.all, L.stats, 64, s);
+    }
+    P.s_cap = s_cap_for(L.d_max);
+    P.roots = L.w.heavy;
+    P.nroots = L.w.ctl + CC_HEAVY_N;
+    P.head = L.w.ctl + CC_HEAVY_HEAD;
+    P.stats = L.w.acc + 4;
+    // the grid cap keeps every wavefront within the global stack slabs carved
+    switch (maxw_for(L.d_max)) {
+        case 4: return launch_piv_m<4, true, 4>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
+        case 8: return launch_piv_m<8, true, 4>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
+        case 16: return launch_piv_m<16, true, 1>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
+        default: return launch_piv_m<32, true, 1>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
+    }
+}
+
+}  // namespace kc
