@@ -156,6 +156,48 @@ KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int
                             int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
                             void* stream);
 
+/* ------------------------------------------------------------- batched */
+
+/* Many independent graphs packed into one CSR (device pointers): graph g owns
+ * vertices [voff[g], voff[g+1]) and its rows reference only its own vertices.
+ * max_degree bounds every vertex degree (it sizes the radix sort on the host, so
+ * no value has to be read back). */
+typedef struct kc_batch {
+    int32_t ngraphs;
+    int32_t n;                 /* total vertices = voff[ngraphs]        */
+    int32_t nnz;               /* total CSR entries                     */
+    int32_t max_degree;
+    const int32_t* row_ptr;    /* [n+1]                                 */
+    const int32_t* col;        /* [nnz]                                 */
+    const int32_t* voff;       /* [ngraphs+1]                           */
+} kc_batch;
+
+#define KC_BATCH_MAX_BUCKETS 8
+
+/* Execution plan by graph size: graphs with voff[g+1] - voff[g] <= n_hi[b] (the
+ * first such bucket b, n_hi ascending) are counted with root scheme scheme[b]
+ * (KC_SCHEME_VC / KC_SCHEME_EC); graphs above the last bound use the last
+ * bucket.  Written by the autotuner; NULL = vertex roots for every graph. */
+typedef struct kc_batch_plan {
+    int32_t nbuckets;
+    int32_t n_hi[KC_BATCH_MAX_BUCKETS];
+    int32_t scheme[KC_BATCH_MAX_BUCKETS];
+} kc_batch_plan;
+
+/* Bytes of device workspace kc_batch_count needs. */
+KC_API size_t kc_batch_workspace(const kc_batch* b, int32_t k);
+
+/* Per-graph k-clique counts of a packed batch (non-pivot traversal, degree
+ * orientation), written to the DEVICE array counts[2*ngraphs] as {lo, hi}
+ * pairs.  Everything runs on `stream` with no host synchronisation, no device
+ * allocation and no memset, so the call can be captured in a HIP graph and
+ * replayed.  A per-graph overflow past 2^64 leaves a non-zero hi word (the
+ * caller's 64-bit check).  Returns KC_EINVAL for k < 1, bad sizes or a plan
+ * with an unknown scheme, KC_ENOMEM for a short workspace, KC_EUNSUPPORTED if
+ * max_degree > KC_MAX_DMAX (rows could not be bitset-encoded). */
+KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t* counts, void* ws, size_t ws_bytes,
+                              const kc_batch_plan* plan, void* stream);
+
 /* Static text for a status code. */
 KC_API const char* kc_strerror(int32_t status);
 

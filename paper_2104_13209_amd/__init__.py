@@ -250,3 +250,133 @@ def dag_to_host(d: Dag):
     m = d.m
     return (d.row_ptr.cpu().numpy(), d.col[:m].cpu().numpy(), d.src[:m].cpu().numpy(),
             d.perm[:d.n].cpu().numpy())
+
+
+# ---------------------------------------------------------------- batched
+
+MAX_BUCKETS = 8
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("ngraphs", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("max_degree", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("voff", ctypes.c_void_p)]
+
+
+class BatchPlan(ctypes.Structure):
+    """kc_batch_plan: root scheme per graph-size bucket (n <= n_hi[b])."""
+    _fields_ = [("nbuckets", ctypes.c_int32), ("n_hi", ctypes.c_int32 * MAX_BUCKETS),
+                ("scheme", ctypes.c_int32 * MAX_BUCKETS)]
+
+    @classmethod
+    def make(cls, buckets):
+        """buckets: list of (n_hi, scheme) in ascending n_hi."""
+        p = cls()
+        p.nbuckets = len(buckets)
+        for i, (hi, sc) in enumerate(buckets):
+            p.n_hi[i] = int(hi)
+            p.scheme[i] = int(sc)
+        return p
+
+    def as_list(self):
+        return [(int(self.n_hi[i]), int(self.scheme[i])) for i in range(self.nbuckets)]
+
+
+@dataclass
+class BatchDev:
+    """Packed independent graphs resident on the device."""
+    ngraphs: int
+    n: int
+    max_degree: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    voff: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def _c(self) -> _Batch:
+        return _Batch(self.ngraphs, self.n, self.nnz, self.max_degree, _ptr(self.row_ptr), _ptr(self.col),
+                      _ptr(self.voff))
+
+
+def batch_to_device(b, device="cuda") -> BatchDev:
+    """Copy a host batch (voff, row_ptr, col arrays) to the device."""
+    deg = np.diff(np.asarray(b.row_ptr, dtype=np.int64))
+    return BatchDev(int(b.voff.shape[0] - 1), int(b.voff[-1]), int(deg.max()) if deg.size else 0,
+                    torch.as_tensor(np.ascontiguousarray(b.row_ptr, np.int32)).to(device),
+                    torch.as_tensor(np.ascontiguousarray(b.col, np.int32)).to(device),
+                    torch.as_tensor(np.ascontiguousarray(b.voff, np.int32)).to(device))
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        L.kc_batch_workspace.argtypes = [ctypes.POINTER(_Batch), ctypes.c_int32]
+        L.kc_batch_workspace.restype = ctypes.c_size_t
+        L.kc_batch_count.argtypes = [ctypes.POINTER(_Batch), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.POINTER(BatchPlan), ctypes.c_void_p]
+        L.kc_batch_count.restype = ctypes.c_int32
+        L._batch_ready = True
+    return L
+
+
+def batch_workspace_bytes(b: BatchDev, k: int) -> int:
+    cb = b._c()
+    return int(_batch_lib().kc_batch_workspace(ctypes.byref(cb), k))
+
+
+def batch_count_async(b: BatchDev, k: int, out: torch.Tensor, ws: torch.Tensor, plan: BatchPlan | None = None,
+                      stream=None) -> None:
+    """Enqueue kc_batch_count: per-graph counts into out (int64 [2*ngraphs] holding
+    unsigned {lo, hi} pairs).  No synchronisation: capturable in a HIP graph."""
+    L = _batch_lib()
+    cb = b._c()
+    st = L.kc_batch_count(ctypes.byref(cb), k, _ptr(out), _ptr(ws), ws.numel(),
+                          ctypes.byref(plan) if plan is not None else None, _stream_handle(stream))
+    if st != OK:
+        raise KcError(st, "kc_batch_count")
+
+
+def counts_from_device(out: torch.Tensor):
+    """Exact per-graph counts (Python ints) from the {lo, hi} pairs."""
+    a = out.cpu().numpy().view(np.uint64).reshape(-1, 2)
+    return [int(lo) | (int(hi) << 64) for lo, hi in a]
+
+
+def batch_count(b: BatchDev, k: int, plan: BatchPlan | None = None):
+    """Per-graph k-clique counts of a batch (eager call + copy back)."""
+    ws = _workspace(batch_workspace_bytes(b, k), b.row_ptr.device)
+    out = torch.empty(2 * b.ngraphs, dtype=torch.int64, device=b.row_ptr.device)
+    batch_count_async(b, k, out, ws, plan)
+    torch.cuda.synchronize()
+    return counts_from_device(out)
+
+
+class BatchGraph:
+    """kc_batch_count captured once in a HIP graph (torch.cuda.CUDAGraph) and replayed."""
+
+    def __init__(self, b: BatchDev, k: int, plan: BatchPlan | None = None):
+        self.b, self.k, self.plan = b, k, plan
+        dev = b.row_ptr.device
+        self.ws = _workspace(batch_workspace_bytes(b, k), dev)
+        self.out = torch.empty(2 * b.ngraphs, dtype=torch.int64, device=dev)
+        # one eager call first (loads kernels, sets attributes), then capture
+        batch_count_async(b, k, self.out, self.ws, plan)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(self.graph, stream=side):
+                batch_count_async(b, k, self.out, self.ws, plan, stream=side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+
+    def replay(self):
+        self.graph.replay()
+
+    def counts(self):
+        torch.cuda.synchronize()
+        return counts_from_device(self.out)

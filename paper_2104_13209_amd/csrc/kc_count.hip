@@ -106,6 +106,56 @@ __global__ void __launch_bounds__(kBlock) k_classify(int nroots_total, int need,
     }
 }
 
+// Width lists: root r goes to list w when its bound on |S| needs 2^w words per
+// bitset row (1, 2, 4, 8, 16 or 32); pass 1 counts, pass 2 appends into
+// consecutive segments of one array (the order inside a list is unspecified).
+__device__ __forceinline__ int width_list(int bound) {
+    return bound <= 32 ? 0 : bound <= 64 ? 1 : bound <= 128 ? 2 : bound <= 256 ? 3 : bound <= 512 ? 4 : 5;
+}
+
+template <bool EC>
+__device__ __forceinline__ int root_bound(int r, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                          const int* __restrict__ src) {
+    if (EC) {
+        const int u = src[r], v = col[r];
+        const int du = row_ptr[u + 1] - row_ptr[u] - 1;
+        const int dv = row_ptr[v + 1] - row_ptr[v];
+        return du < dv ? du : dv;
+    }
+    return row_ptr[r + 1] - row_ptr[r];
+}
+
+template <bool EC, bool FILL>
+__global__ void __launch_bounds__(kBlock) k_classify_w(int nroots_total, int need, const int* __restrict__ row_ptr,
+                                                      const int* __restrict__ col, const int* __restrict__ src,
+                                                      int* lists, int* ctl) {
+    const int lane = threadIdx.x & 63;
+    int off[kWidthLists];
+    if (FILL) {
+        int run = 0;
+        for (int j = 0; j < kWidthLists; j++) {
+            off[j] = run;
+            run += ctl[CC_WN0 + j];
+        }
+    }
+    for (int base = blockIdx.x * blockDim.x; base < nroots_total; base += gridDim.x * blockDim.x) {
+        const int r = base + threadIdx.x;
+        int lst = -1;
+        if (r < nroots_total) {
+            const int bound = root_bound<EC>(r, row_ptr, col, src);
+            if (bound >= need && bound >= 0) lst = width_list(bound);
+        }
+        for (int j = 0; j < kWidthLists; j++) {
+            const unsigned long long m = __ballot(lst == j);
+            if (m == 0ull) continue;
+            int b = 0;
+            if (lane == 0) b = atomicAdd(&ctl[(FILL ? CC_WC0 : CC_WN0) + j], __popcll(m));
+            b = __shfl(b, 0);
+            if (FILL && lst == j) lists[off[j] + b + __popcll(m & lanemask_lt())] = r;
+        }
+    }
+}
+
 // ------------------------------------------------------------- traversal
 
 // G: lanes per group; MAXW: bitset words per row this instantiation handles;
@@ -402,15 +452,71 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     int cblocks = div_up(nroots, kBlock);
     if (cblocks > device_cus() * 8) cblocks = device_cus() * 8;
     if (cblocks < 1) cblocks = 1;
-    if (ec)
+    bool lane_path = pivot_all < 0 && (o ? o->width : 0) <= 1;
+    if (lane_path) {
+        // the widest list must fit one wavefront's LDS; otherwise use the group walk
+        int top = 0;
+        while (top < kWidthLists - 1 && (32 << top) < d->d_max) top++;
+        const bool deep = k >= (ec ? 3 : 2) + 4;
+        if (lane_lds_bytes(1 << top, k, ec, deep && top >= 2) > 160 * 1024) lane_path = false;
+    }
+    if (lane_path) {
+        KC_CHECK(hipMemsetAsync(w.active, 0xff, sizeof(int) * w.nactive, s));
+        if (k >= (ec ? 3 : 2) + 4) {
+            KC_CHECK(hipMemsetAsync(w.task_ctr, 0, sizeof(int) * static_cast<size_t>(nroots), s));
+            KC_CHECK(hipMemsetAsync(w.task_tot, 0, sizeof(int) * static_cast<size_t>(nroots), s));
+        }
+        if (ec)
+            k_classify_w<true, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+        else
+            k_classify_w<false, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+    } else if (ec) {
         k_classify<true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
-    else
+    } else {
         k_classify<false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
+    }
     KC_CHECK(hipGetLastError());
-    if (prof) KC_CHECK(hipEventRecord(pe->ev[1], s));
+    if (prof && !lane_path) KC_CHECK(hipEventRecord(pe->ev[1], s));
 
     int st = KC_OK;
-    if (pivot_all < 0) {
+    if (lane_path) {
+        // lane walks over the width lists, widest first so that the largest roots
+        // start early; profile: heavy = lists with >= 4 words, light = 1-2 words
+        if (ec)
+            k_classify_w<true, true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+        else
+            k_classify_w<false, true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+        KC_CHECK(hipGetLastError());
+        if (prof) KC_CHECK(hipEventRecord(pe->ev[1], s));
+        const int p0 = ec ? 3 : 2;
+        const bool deep = k >= p0 + 4;
+        int top = 0;
+        while (top < kWidthLists - 1 && (32 << top) < d->d_max) top++;
+        for (int lst = top; lst >= 0; lst--) {
+            if (lst == 1 && prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
+            LaneLaunch L;
+            L.k = k;
+            L.ec = ec;
+            L.pair = deep && lst >= 2;
+            L.stats = stats;
+            L.maxw = 1 << lst;
+            L.list = lst;
+            L.row_ptr = d->row_ptr;
+            L.col = d->col;
+            L.src = d->src;
+            L.lists = w.light;
+            L.counts = w.ctl + CC_WN0;
+            L.head = w.ctl + CC_WH0 + lst;
+            L.task_ctr = w.task_ctr;
+            L.task_tot = w.task_tot;
+            L.active = w.active;
+            L.acc = w.acc;
+            L.stats_ptr = w.acc + (lst >= 2 ? 4 : 2);
+            st = lane_launch(L, s);
+            if (st != KC_OK) return st;
+        }
+        if (prof && top < 1) KC_CHECK(hipEventRecord(pe->ev[2], s));
+    } else if (pivot_all < 0) {
         GoParams P;
         P.n = d->n;
         P.m = d->m;
@@ -460,7 +566,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         }
     }
     if (prof) {
-        if (d->d_max <= kLightCap) KC_CHECK(hipEventRecord(pe->ev[2], s));
+        if (!lane_path && d->d_max <= kLightCap) KC_CHECK(hipEventRecord(pe->ev[2], s));
         KC_CHECK(hipEventRecord(pe->ev[3], s));
     }
     KC_CHECK(hipMemcpyAsync(res, w.acc, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -471,15 +577,26 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     KC_CHECK(hipStreamSynchronize(s));
     if (prof) {
         KC_CHECK(hipEventElapsedTime(&prof->ms_classify, pe->ev[0], pe->ev[1]));
-        KC_CHECK(hipEventElapsedTime(&prof->ms_light, pe->ev[1], pe->ev[2]));
-        KC_CHECK(hipEventElapsedTime(&prof->ms_heavy, pe->ev[2], pe->ev[3]));
+        if (lane_path) {   // heavy lists run first
+            KC_CHECK(hipEventElapsedTime(&prof->ms_heavy, pe->ev[1], pe->ev[2]));
+            KC_CHECK(hipEventElapsedTime(&prof->ms_light, pe->ev[2], pe->ev[3]));
+        } else {
+            KC_CHECK(hipEventElapsedTime(&prof->ms_light, pe->ev[1], pe->ev[2]));
+            KC_CHECK(hipEventElapsedTime(&prof->ms_heavy, pe->ev[2], pe->ev[3]));
+        }
         KC_CHECK(hipEventElapsedTime(&prof->ms_total, pe->ev[0], pe->ev[3]));
         for (int i = 0; i < 2; i++) {
             prof->nodes[i] = stats ? res[2 + 2 * i] : 0;
             prof->word_ops[i] = stats ? res[3 + 2 * i] : 0;
         }
-        prof->light_roots = hctl[CC_LIGHT_N];
-        prof->heavy_roots = hctl[CC_HEAVY_N];
+        if (lane_path) {
+            prof->light_roots = hctl[CC_WN0] + hctl[CC_WN0 + 1];
+            prof->heavy_roots = 0;
+            for (int j = 2; j < kWidthLists; j++) prof->heavy_roots += hctl[CC_WN0 + j];
+        } else {
+            prof->light_roots = hctl[CC_LIGHT_N];
+            prof->heavy_roots = hctl[CC_HEAVY_N];
+        }
     }
     return KC_OK;
 }

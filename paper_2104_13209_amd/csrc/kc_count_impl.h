@@ -7,6 +7,8 @@ namespace kc {
 
 constexpr int kLightCap = 64;          // |S| bound of the light root list
 constexpr int kPivBlocksPerCU = 8;     // grid cap of the heavy pivot kernel (sizes its stacks)
+constexpr int kLaneWavesPerCU = 32;    // grid cap of the lane-walk kernel (sizes its registry)
+constexpr int kWidthLists = 6;         // root lists by bitset words per row: 1, 2, 4, 8, 16, 32
 
 enum CountCtl {
     CC_LIGHT_N = 0,      // light root count
@@ -14,8 +16,18 @@ enum CountCtl {
     CC_LIGHT_HEAD = 2,   // light queue head
     CC_HEAVY_HEAD = 3,   // heavy queue head
     CC_FLAGS = 4,        // bit 0: a binomial beyond 128 bits was used
-    CC_WORDS = 8
+    CC_WN0 = 8,          // width lists: root counts (8..13)
+    CC_WC0 = 16,         // width lists: fill cursors (16..21)
+    CC_WH0 = 24,         // width lists: queue heads (24..29)
+    CC_WORDS = 32
 };
+
+// Saved levels a depth-first walk starting at path length `first` may need:
+// levels are saved only while the path is shorter than k - 2.
+inline int k_levels(int k, int first) {
+    const int lv = k - 2 - first;
+    return lv < 1 ? 1 : lv;
+}
 
 __host__ __device__ constexpr int b_stride_of(int maxw) { return (maxw > 1 && (maxw % 2) == 0) ? maxw + 1 : maxw; }
 
@@ -42,6 +54,10 @@ struct CountWs {
     unsigned long long* binom;    // (binom_n + 1)^2 x {lo, hi}: C(i, j) at [i * (binom_n + 1) + j]
     unsigned char* big;           // same shape: 1 if C(i, j) needs more than 128 bits
     unsigned int* gstack;         // heavy pivot stacks, one slab per resident wavefront
+    int* task_ctr;                // lane walk, pair tasks: claimed tasks per root
+    int* task_tot;                // lane walk, pair tasks: total tasks + 1 per root (0 = unpublished)
+    int* active;                  // lane walk: root slot owned by each wavefront (-1 = none)
+    int nactive;
     int binom_n;
     size_t slab_words;
     int slabs;
@@ -55,6 +71,10 @@ inline CountWs carve_count(void* ws, const kc_dag* d, bool pivot, size_t* bytes)
     w.acc = c.take<unsigned long long>(8);
     w.light = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
     w.heavy = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
+    w.task_ctr = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
+    w.task_tot = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
+    w.nactive = device_cus() * kLaneWavesPerCU;
+    w.active = c.take<int>(static_cast<size_t>(w.nactive));
     if (pivot) {
         const int s_cap = s_cap_for(d->d_max);
         w.binom_n = s_cap + 2;
@@ -88,5 +108,45 @@ struct PivLaunch {
 
 int pivot_binom_table(const CountWs& w, hipStream_t s);
 int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s);
+
+// Launch description for the lane-walk graph-orientation kernel (kc_lane.hip).
+struct LaneLaunch {
+    int k;
+    bool ec;
+    bool pair;            // pair tasks from a global per-root counter + helping
+    bool stats;
+    int maxw;             // bitset words per row of this list
+    int list;             // list index (0..kWidthLists-1)
+    const int* row_ptr;
+    const int* col;
+    const int* src;
+    const int* lists;     // all width lists back to back
+    const int* counts;    // ctl + CC_WN0
+    int* head;            // ctl + CC_WH0 + list
+    int* task_ctr;
+    int* task_tot;
+    int* active;
+    unsigned long long* acc;
+    unsigned long long* stats_ptr;
+    unsigned long long* gacc = nullptr;   // batched: per-graph counters
+    const int* gid = nullptr;             // batched: graph of each DAG vertex
+};
+
+int lane_launch(const LaneLaunch& L, hipStream_t s);
+
+// Capture-safe degree orientation (kc_orient.hip).
+size_t orient_async_workspace(int n, int nnz);
+int orient_degree_async(int n, int nnz, const int* row_ptr, const int* col, int key_bits, int* out_row_ptr,
+                        int* out_col, int* out_src, int* out_perm, void* ws, hipStream_t s);
+
+// LDS bytes one lane-walk wavefront needs for a list of `maxw` words per row.
+inline size_t lane_lds_bytes(int maxw, int k, bool ec, bool pair) {
+    const int s_cap = 32 * maxw;
+    const int slot = maxw + 1;
+    const int first = (ec ? 3 : 2) + (pair ? 1 : 0);
+    const int words = 16 + s_cap + s_cap * b_stride_of(maxw) + (pair ? s_cap + 1 : 0) + 64 * slot +
+                      k_levels(k, first) * slot * 64;
+    return static_cast<size_t>(words) * 4;
+}
 
 }  // namespace kc

@@ -1,0 +1,436 @@
+// Graph-orientation traversal (paper Fig. 2) with lane-private depth-first
+// walks and in-wavefront work donation, for gfx950 wave64.
+//
+// Each wavefront owns one root at a time: it extracts S and the bitset rows B
+// into its own LDS (Sec. 2.4, 3.4), then every lane walks subtrees on its own:
+// lane state is the current level's remaining candidate set R (MAXW words in
+// registers), the path length p, and an explicit stack of saved levels in LDS
+// (Sec. 3.3).  A step takes the lowest set bit v of R, clears it, and forms
+// Y = R & B[v] (rows are upper triangular, so this is I cap Adj(v) of Fig. 2);
+// at the last level it adds popcount(Y), otherwise it descends into Y, saving R
+// only when R still holds candidates.
+//
+// Work sources, in order:
+//   tasks      vertex tasks i (the branch through S[i]) from a per-wavefront
+//              counter; for deep trees on wide roots, pair tasks (i, j) (the
+//              branch through S[i], S[j]) from a global per-root counter, so that
+//              other wavefronts can join a root that is still being counted;
+//   donation   when some lanes have nothing left and others are deep in a
+//              subtree, the r-th idle lane receives the shallowest saved level of
+//              the r-th busy lane through an LDS mailbox (ballot ranks pair them;
+//              no atomics are needed inside a wavefront);
+//   helping    a wavefront whose root queue is empty joins a root whose pair tasks
+//              are not all claimed (it extracts its own copy of that root).
+#include "kc_count_impl.h"
+#include "kc_extract.h"
+
+namespace kc {
+namespace {
+
+struct LaneParams {
+    int k;
+    int s_cap;
+    int levels;                     // saved levels per lane
+    int list;                       // index of this root list
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ col;
+    const int* __restrict__ src;
+    const int* __restrict__ lists;  // all root lists, back to back
+    const int* __restrict__ counts; // root count of every list
+    int* head;                      // this list's queue head
+    int* task_ctr;                  // pair mode: per-root claimed-task counters
+    int* task_tot;                  // pair mode: per-root task totals + 1 (0 = not published)
+    int* active;                    // pair mode: root slot owned by each wavefront, -1 if none
+    unsigned long long* acc;        // [lo, hi]
+    unsigned long long* stats;      // [nodes, words]
+    unsigned long long* gacc;       // batched: per-graph {lo, hi}; null otherwise
+    const int* __restrict__ gid;    // batched: graph of each DAG vertex
+};
+
+// Batched counts: the lanes' partial counts of one root belong to one graph; add
+// them to that graph's 128-bit counter and restart from zero.
+__device__ __forceinline__ void flush_root(const LaneParams& P, int g, unsigned long long& acc) {
+    unsigned long long lo, hi;
+    wave_sum_u128(acc, lo, hi);
+    if (__lane_id() == 0 && (lo | hi)) atomic_add_u128(P.gacc + 2 * g, P.gacc + 2 * g + 1, lo, hi);
+    acc = 0;
+}
+
+// Index of the r-th set bit (0-based) of x, r < popc(x).
+__device__ __forceinline__ int select_bit(unsigned int x, int r) {
+    int pos = 0;
+    int c = __popc(x & 0xffffu);
+    if (r >= c) { r -= c; x >>= 16; pos += 16; }
+    c = __popc(x & 0xffu);
+    if (r >= c) { r -= c; x >>= 8; pos += 8; }
+    c = __popc(x & 0xfu);
+    if (r >= c) { r -= c; x >>= 4; pos += 4; }
+    c = __popc(x & 0x3u);
+    if (r >= c) { r -= c; x >>= 2; pos += 2; }
+    c = static_cast<int>(x & 1u);
+    if (r >= c) { pos += 1; }
+    return pos;
+}
+
+// MAXW: bitset words per row of this root list; EC: edge roots; PAIR: pair
+// tasks + helping (deep trees on wide roots); STATS: count expanded nodes.
+template <int MAXW, bool EC, bool PAIR, bool STATS>
+__global__ void __launch_bounds__(64) k_lane(LaneParams P) {
+    constexpr int STRIDE = b_stride_of(MAXW);
+    constexpr int SLOT = MAXW + 1;                  // saved level: R words + p
+    extern __shared__ unsigned int lds[];
+    const int lane = threadIdx.x & 63;
+    const int s_cap = P.s_cap;
+    unsigned int* base = lds;
+    int* ctl = reinterpret_cast<int*>(base);
+    int* S = reinterpret_cast<int*>(base + 16);
+    unsigned int* B = base + 16 + s_cap;
+    int* pre = reinterpret_cast<int*>(B + s_cap * STRIDE);
+    unsigned int* mbox = B + s_cap * STRIDE + (PAIR ? s_cap + 1 : 0);
+    unsigned int* stk = mbox + 64 * SLOT;           // [level][slot word][lane]
+    const int k = P.k;
+    const int p0 = EC ? 3 : 2;
+    int list_off = 0;
+    for (int j = 0; j < P.list; j++) list_off += P.counts[j];
+    const int* roots = P.lists + list_off;
+    const int nroots = P.counts[P.list];
+    int* tctr = P.task_ctr + list_off;
+    int* ttot = P.task_tot + list_off;
+    const int nwaves = gridDim.x;                   // one wavefront per block
+    const unsigned long long lt = lanemask_lt();
+
+    unsigned long long acc = 0, nodes = 0, wsum = 0;
+    bool helping = false;
+
+    for (;;) {
+        // ---------------------------------------------------------- root
+        int slot = -1;
+        if (!helping) {
+            int r = 0;
+            if (lane == 0) r = atomicAdd(P.head, 1);
+            r = __shfl(r, 0);
+            if (r < nroots) slot = r;
+            else if (PAIR) helping = true;
+            else break;
+        }
+        if (PAIR && helping) {
+            // join the in-progress root with the most unclaimed pair tasks
+            unsigned long long best = 0;
+            for (int b0 = 0; b0 < nwaves; b0 += 64) {
+                const int e = b0 + lane;
+                if (e < nwaves) {
+                    const int sl = ld_acquire(&P.active[e]);
+                    if (sl >= 0) {
+                        const int tot = ld_acquire(&ttot[sl]);
+                        const int rem = tot - 1 - ld_acquire(&tctr[sl]);
+                        if (tot > 0 && rem > 0) {
+                            const unsigned long long key = (static_cast<unsigned long long>(rem) << 32) |
+                                                           static_cast<unsigned int>(sl);
+                            best = key > best ? key : best;
+                        }
+                    }
+                }
+            }
+            best = wave_max(best);
+            if (best == 0ull) break;
+            slot = static_cast<int>(best & 0xffffffffu);
+        }
+        const int rid = roots[slot];
+        const int graph = P.gacc ? P.gid[EC ? P.src[rid] : rid] : 0;
+        extract_set<1, EC>(rid, P.row_ptr, P.col, P.src, lane, S, &ctl[1]);
+        const int s = ctl[1];
+        if (EC && k == 3) {
+            if (lane == 0 && !helping) acc += static_cast<unsigned long long>(s);
+            if (P.gacc) flush_root(P, graph, acc);
+            wave_sync_lds();
+            continue;
+        }
+        extract_rows<1, false>(s, P.row_ptr, P.col, lane, S, B, STRIDE);
+        const unsigned long long W = static_cast<unsigned long long>((s + 31) >> 5);
+
+        int total = s;                                   // tasks of this root
+        if (PAIR) {
+            // pre[i] = number of pair tasks before row i
+            int run = 0;
+            for (int b0 = 0; b0 < s; b0 += 64) {
+                const int i = b0 + lane;
+                int c = 0;
+                if (i < s) {
+#pragma unroll
+                    for (int t = 0; t < MAXW; t++) c += __popc(B[i * STRIDE + t]);
+                }
+                int inc = c;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(inc, off, 64);
+                    if (lane >= off) inc += y;
+                }
+                if (i < s) pre[i] = run + inc - c;
+                run += __shfl(inc, 63);
+            }
+            if (lane == 0) pre[s] = run;
+            wave_sync_lds();
+            total = run;
+            if (!helping && lane == 0) {
+                __hip_atomic_store(&ttot[slot], run + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&P.active[blockIdx.x], slot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+
+        // ---------------------------------------------------- traversal
+        unsigned int R[MAXW];
+#pragma unroll
+        for (int t = 0; t < MAXW; t++) R[t] = 0u;
+        int p = 0, depth = 0, sbase = 0;
+        bool out = false;                                // no task left for this lane
+        int next_task = 0;                               // vertex tasks: wave counter
+
+        for (;;) {
+            bool emp = true;
+#pragma unroll
+            for (int t = 0; t < MAXW; t++) emp &= R[t] == 0u;
+            // pop a saved level
+            if (emp && depth > sbase) {
+                depth--;
+                const unsigned int* f = stk + depth * SLOT * 64 + lane;
+#pragma unroll
+                for (int t = 0; t < MAXW; t++) R[t] = f[t * 64];
+                p = static_cast<int>(f[MAXW * 64]);
+                emp = false;
+            }
+            // claim tasks for lanes that have nothing
+            const unsigned long long needy = __ballot(emp && !out);
+            if (needy) {
+                const int nn = __popcll(needy);
+                const int rank = __popcll(needy & lt);
+                int t0;
+                if (PAIR) {
+                    int b = 0;
+                    if (lane == 0) b = atomicAdd(&tctr[slot], nn);
+                    t0 = __shfl(b, 0);
+                } else {
+                    t0 = next_task;
+                    next_task += nn;
+                }
+                if (emp && !out) {
+                    const int t = t0 + rank;
+                    if (t < total) {
+                        sbase = depth = 0;
+                        if (PAIR) {
+                            // pair task t -> (i, j): row i by binary search of pre[],
+                            // j the (t - pre[i])-th set bit of B[i]
+                            int lo = 0, hi = s;                     // pre[lo] <= t < pre[hi]
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (pre[mid] <= t) lo = mid; else hi = mid;
+                            }
+                            const int i = lo;
+                            int r = t - pre[i], j = 0;
+                            bool got = false;
+#pragma unroll
+                            for (int w = 0; w < MAXW; w++) {
+                                const unsigned int x = B[i * STRIDE + w];
+                                const int c = __popc(x);
+                                if (!got && r < c) { j = 32 * w + select_bit(x, r); got = true; }
+                                if (!got) r -= c;
+                            }
+                            unsigned int c2 = 0;
+#pragma unroll
+                            for (int w = 0; w < MAXW; w++) {
+                                R[w] = B[i * STRIDE + w] & B[j * STRIDE + w];
+                                c2 += __popc(R[w]);
+                            }
+                            p = p0 + 1;
+                            if (STATS) { nodes += 1; wsum += W; }
+                            if (p + 1 == k) {
+                                acc += c2;
+#pragma unroll
+                                for (int w = 0; w < MAXW; w++) R[w] = 0u;
+                            }
+                        } else {
+                            unsigned int c2 = 0;
+#pragma unroll
+                            for (int w = 0; w < MAXW; w++) {
+                                R[w] = B[t * STRIDE + w];
+                                c2 += __popc(R[w]);
+                            }
+                            p = p0;
+                            if (p + 1 == k) {
+                                acc += c2;
+#pragma unroll
+                                for (int w = 0; w < MAXW; w++) R[w] = 0u;
+                            }
+                        }
+                    } else {
+                        out = true;
+                    }
+                }
+            }
+            // donation: the r-th idle lane takes the shallowest saved level of the
+            // r-th lane that has one
+            bool idle = true;
+#pragma unroll
+            for (int t = 0; t < MAXW; t++) idle &= R[t] == 0u;
+            idle = idle && depth <= sbase && out;
+            const unsigned long long idle_m = __ballot(idle);
+            const unsigned long long donor_m = __ballot(depth > sbase);
+            if (idle_m != 0ull && donor_m != 0ull) {
+                const int n = min(__popcll(idle_m), __popcll(donor_m));
+                if (depth > sbase) {
+                    const int rd = __popcll(donor_m & lt);
+                    if (rd < n) {
+                        const unsigned int* f = stk + sbase * SLOT * 64 + lane;
+#pragma unroll
+                        for (int t = 0; t <= MAXW; t++) mbox[rd * SLOT + t] = f[t * 64];
+                        sbase++;
+                    }
+                }
+                wave_sync_lds();
+                if (idle) {
+                    const int ri = __popcll(idle_m & lt);
+                    if (ri < n) {
+#pragma unroll
+                        for (int t = 0; t < MAXW; t++) R[t] = mbox[ri * SLOT + t];
+                        p = static_cast<int>(mbox[ri * SLOT + MAXW]);
+                        depth = sbase = 0;
+                    }
+                }
+                wave_sync_lds();
+            }
+            // done with this root when no lane holds work and no task is left
+            bool busy = false;
+#pragma unroll
+            for (int t = 0; t < MAXW; t++) busy |= R[t] != 0u;
+            busy = busy || depth > sbase;
+            if (__ballot(busy || !out) == 0ull) break;
+            if (busy) {
+                bool has = false;
+#pragma unroll
+                for (int t = 0; t < MAXW; t++) has |= R[t] != 0u;
+                if (has) {
+                    // expand the lowest candidate v
+                    int v = 0;
+                    bool got = false;
+#pragma unroll
+                    for (int t = 0; t < MAXW; t++) {
+                        if (!got && R[t] != 0u) {
+                            v = 32 * t + __ffs(R[t]) - 1;
+                            R[t] &= R[t] - 1u;
+                            got = true;
+                        }
+                    }
+                    unsigned int Y[MAXW];
+                    unsigned int c = 0;
+                    bool yany = false;
+#pragma unroll
+                    for (int t = 0; t < MAXW; t++) {
+                        Y[t] = R[t] ? (R[t] & B[v * STRIDE + t]) : 0u;
+                        c += __popc(Y[t]);
+                        yany |= Y[t] != 0u;
+                    }
+                    if (STATS) { nodes += 1; wsum += W; }
+                    if (p + 2 == k) {
+                        acc += c;
+                    } else if (yany) {
+                        bool rany = false;
+#pragma unroll
+                        for (int t = 0; t < MAXW; t++) rany |= R[t] != 0u;
+                        if (rany) {
+                            unsigned int* f = stk + depth * SLOT * 64 + lane;
+#pragma unroll
+                            for (int t = 0; t < MAXW; t++) f[t * 64] = R[t];
+                            f[MAXW * 64] = static_cast<unsigned int>(p);
+                            depth++;
+                        }
+#pragma unroll
+                        for (int t = 0; t < MAXW; t++) R[t] = Y[t];
+                        p++;
+                    }
+                }
+            }
+        }
+        if (PAIR && !helping && lane == 0)
+            __hip_atomic_store(&P.active[blockIdx.x], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (P.gacc) flush_root(P, graph, acc);
+        wave_sync_lds();
+    }
+
+    unsigned long long lo, hi;
+    wave_sum_u128(acc, lo, hi);
+    if (lane == 0) atomic_add_u128(P.acc, P.acc + 1, lo, hi);
+    if (STATS) {
+        nodes = wave_sum(nodes);
+        wsum = wave_sum(wsum);
+        if (lane == 0) {
+            atomicAdd(P.stats, nodes);
+            atomicAdd(P.stats + 1, wsum);
+        }
+    }
+}
+
+template <int MAXW, bool EC, bool PAIR>
+int launch_lane_t(const LaneParams& base, bool stats, hipStream_t s) {
+    constexpr int SLOT = MAXW + 1;
+    LaneParams P = base;
+    P.s_cap = 32 * MAXW;
+    const int words = 16 + P.s_cap + P.s_cap * b_stride_of(MAXW) + (PAIR ? P.s_cap + 1 : 0) + 64 * SLOT +
+                      P.levels * SLOT * 64;
+    const size_t lds_bytes = static_cast<size_t>(words) * sizeof(unsigned int);
+    (void)SLOT;
+    if (lds_bytes > 160 * 1024) return KC_EUNSUPPORTED;
+    auto kern = stats ? k_lane<MAXW, EC, PAIR, true> : k_lane<MAXW, EC, PAIR, false>;
+    if (lds_bytes > 64 * 1024)
+        KC_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)));
+    int occ = 0;
+    KC_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64, lds_bytes));
+    if (occ < 1) return KC_EUNSUPPORTED;
+    if (occ > kLaneWavesPerCU) occ = kLaneWavesPerCU;   // the registry holds one entry per wavefront
+    kern<<<device_cus() * occ, 64, lds_bytes, s>>>(P);
+    KC_CHECK(hipGetLastError());
+    return KC_OK;
+}
+
+template <int MAXW>
+int launch_lane_m(const LaneParams& P, bool ec, bool pair, bool stats, hipStream_t s) {
+    if (ec) return pair ? launch_lane_t<MAXW, true, true>(P, stats, s) : launch_lane_t<MAXW, true, false>(P, stats, s);
+    return pair ? launch_lane_t<MAXW, false, true>(P, stats, s) : launch_lane_t<MAXW, false, false>(P, stats, s);
+}
+
+}  // namespace
+
+int lane_launch(const LaneLaunch& L, hipStream_t s) {
+    LaneParams P;
+    P.k = L.k;
+    P.row_ptr = L.row_ptr;
+    P.col = L.col;
+    P.src = L.src;
+    P.list = L.list;
+    P.lists = L.lists;
+    P.counts = L.counts;
+    P.head = L.head;
+    P.task_ctr = L.task_ctr;
+    P.task_tot = L.task_tot;
+    P.active = L.active;
+    P.acc = L.acc;
+    P.stats = L.stats_ptr;
+    P.gacc = L.gacc;
+    P.gid = L.gid;
+    const int p0 = L.ec ? 3 : 2;
+    // pair tasks start at path length p0 + 1; vertex tasks at p0.  Saved levels
+    // are needed for path lengths below k - 2.
+    const int first = L.pair ? p0 + 1 : p0;
+    P.levels = k_levels(L.k, first);
+    P.s_cap = 0;
+    switch (L.maxw) {
+        case 1: return launch_lane_m<1>(P, L.ec, L.pair, L.stats, s);
+        case 2: return launch_lane_m<2>(P, L.ec, L.pair, L.stats, s);
+        case 4: return launch_lane_m<4>(P, L.ec, L.pair, L.stats, s);
+        case 8: return launch_lane_m<8>(P, L.ec, L.pair, L.stats, s);
+        case 16: return launch_lane_m<16>(P, L.ec, L.pair, L.stats, s);
+        case 32: return launch_lane_m<32>(P, L.ec, L.pair, L.stats, s);
+        default: return KC_EINVAL;
+    }
+}
+
+}  // namespace kc

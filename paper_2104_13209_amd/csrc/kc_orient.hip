@@ -439,7 +439,57 @@ int exclusive_scan(int count, const int* in, int* out, int* tiles, int* total, h
     return KC_OK;
 }
 
+__global__ void __launch_bounds__(kBlock) k_zero(int* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(int* dst, const int* src, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
 }  // namespace
+
+size_t orient_async_workspace(int n, int nnz) {
+    size_t bytes = 0;
+    carve(nullptr, n, nnz, &bytes);
+    return bytes;
+}
+
+// Degree-order orientation with no host synchronisation (every launch size is
+// known on the host: `key_bits` bounds the bit length of the largest degree), so
+// it can be captured in a HIP graph.  Writes row_ptr, col, src, perm; the max
+// out-degree stays on the device (ws control word), unread.
+int orient_degree_async(int n, int nnz, const int* row_ptr, const int* col, int key_bits, int* out_row_ptr,
+                        int* out_col, int* out_src, int* out_perm, void* ws, hipStream_t s) {
+    size_t need = 0;
+    OrientWs w = carve(ws, n, nnz, &need);
+    if (n <= 0) return KC_EINVAL;
+    k_zero<<<1, kBlock, 0, s>>>(w.ctl, CTL_WORDS);
+    k_degree_key<<<grid_for_threads(n), kBlock, 0, s>>>(n, row_ptr, w.key_a, w.val_a, w.ctl);
+    const int ntiles = div_up(n, kTile);
+    int *kin = w.key_a, *vin = w.val_a, *kout = w.key_b, *vout = w.val_b;
+    for (int bit = 0; bit < key_bits; bit++) {
+        k_tile_sum<<<ntiles, kBlock, 0, s>>>(n, kin, bit, 1, w.tiles);
+        k_scan_tiles<<<1, kBlock, 0, s>>>(ntiles, w.tiles, w.ctl + CTL_ZEROS);
+        k_radix_scatter<<<ntiles, kBlock, 0, s>>>(n, bit, kin, vin, w.tiles, w.ctl + CTL_ZEROS, kout, vout);
+        int* t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+    }
+    k_copy<<<grid_for_threads(n), kBlock, 0, s>>>(out_perm, vin, n);
+    k_rank<<<grid_for_threads(n), kBlock, 0, s>>>(n, out_perm, w.rank);
+    k_outdeg<<<grid_for_waves(n), kBlock, 0, s>>>(n, row_ptr, col, out_perm, w.rank, w.outdeg, w.ctl);
+    KC_CHECK(hipGetLastError());
+    int st = exclusive_scan(n, w.outdeg, out_row_ptr, w.tiles, w.ctl + CTL_ZEROS, s);
+    if (st != KC_OK) return st;
+    if (nnz > 0) {
+        k_fill<<<grid_for_waves(n), kBlock, 0, s>>>(n, row_ptr, col, out_perm, w.rank, out_row_ptr, out_col,
+                                                   out_src, w.tmp, w.ctl);
+        k_sort_long_rows<<<grid_for_waves(n), kBlock, 0, s>>>(n, out_row_ptr, w.tmp, out_col, out_src);
+        KC_CHECK(hipGetLastError());
+    }
+    return KC_OK;
+}
+
 }  // namespace kc
 
 using namespace kc;

@@ -56,6 +56,13 @@ def _load():
         lib.synth_permutation.restype = None
         lib.synth_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.synth_uniform.restype = ctypes.c_double
+        lib.synth_batch.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, i32p,
+                                    P(ctypes.c_int64), P(i32p)]
+        lib.synth_batch.restype = ctypes.c_int64
+        lib.synth_batch_vertices.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_double, ctypes.c_double]
+        lib.synth_batch_vertices.restype = ctypes.c_int64
         lib.synth_free.argtypes = [ctypes.c_void_p]
         lib.synth_free.restype = None
         _lib = lib
@@ -266,6 +273,59 @@ def random_bipartite(a: int, b: int, p: float, seed: int) -> Graph:
     side = e < a
     keep = side[:, 0] != side[:, 1]
     return from_pairs(a + b, e[keep], "bip(%d,%d,%g)" % (a, b, p))
+
+
+# ---------------------------------------------------------------- batches
+
+@dataclass
+class Batch:
+    """Independent graphs packed into one CSR: graph g owns vertices
+    [voff[g], voff[g+1]) and its rows hold only its own vertices (global ids)."""
+    voff: np.ndarray     # int32[ngraphs+1]
+    row_ptr: np.ndarray  # int32[N+1]
+    col: np.ndarray      # int32[nnz]
+
+    @property
+    def ngraphs(self) -> int:
+        return int(self.voff.shape[0] - 1)
+
+    @property
+    def n(self) -> int:
+        return int(self.voff[-1])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    def graph(self, g: int) -> Graph:
+        a, b = int(self.voff[g]), int(self.voff[g + 1])
+        rp = self.row_ptr[a:b + 1].astype(np.int64) - int(self.row_ptr[a])
+        col = self.col[int(self.row_ptr[a]):int(self.row_ptr[b])] - a
+        return Graph(b - a, rp.astype(np.int32), col.astype(np.int32), "batch[%d]" % g)
+
+
+def batch(ngraphs: int, seed: int = 4, nmin: int = 50, nmax: int = 5000, dmin: float = 8.0,
+          dmax: float = 64.0, gamma: float = 2.3) -> Batch:
+    """Batched workload: `ngraphs` graphs with vertex counts log-uniform on
+    [nmin, nmax], half Erdos-Renyi and half Chung-Lu (degree exponent gamma,
+    weights capped at sqrt(n * mean)), mean degree uniform on [dmin, dmax]
+    capped at n - 1, packed into one CSR."""
+    lib = _load()
+    V = int(lib.synth_batch_vertices(ngraphs, seed, nmin, nmax, dmin, dmax))
+    voff = np.zeros(ngraphs + 1, dtype=np.int32)
+    row_ptr = np.zeros(V + 1, dtype=np.int64)
+    ptr = ctypes.POINTER(ctypes.c_int32)()
+    nnz = lib.synth_batch(ngraphs, seed, nmin, nmax, dmin, dmax, gamma,
+                          voff.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(ptr))
+    if nnz < 0:
+        raise MemoryError("batch generation failed")
+    if nnz > np.iinfo(np.int32).max:
+        lib.synth_free(ptr)
+        raise ValueError("batch too large for int32 CSR offsets")
+    col = np.ctypeslib.as_array(ptr, shape=(max(nnz, 1),))[:nnz].copy()
+    lib.synth_free(ptr)
+    return Batch(voff, row_ptr.astype(np.int32), col)
 
 
 # ------------------------------------------------------------- workload shapes

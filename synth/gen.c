@@ -192,3 +192,130 @@ double synth_uniform(uint64_t seed, uint64_t i) {
     sm64 r = sm64_stream(seed, i);
     return sm64_unif(&r);
 }
+
+/* ------------------------------------------------------------------ batch */
+
+static int cmp_i32(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Rows sorted ascending: insertion sort for short rows, qsort otherwise. */
+static void sort_row(int32_t* r, int64_t len) {
+    if (len > 48) { qsort(r, (size_t)len, sizeof(int32_t), cmp_i32); return; }
+    for (int64_t i = 1; i < len; i++) {
+        int32_t x = r[i];
+        int64_t j = i - 1;
+        while (j >= 0 && r[j] > x) { r[j + 1] = r[j]; j--; }
+        r[j + 1] = x;
+    }
+}
+
+/* Parameters of graph g of a batch: vertex count log-uniform on [nmin, nmax],
+ * kind 0 = Erdos-Renyi / 1 = Chung-Lu (50/50), mean degree uniform on
+ * [dmin, dmax] capped at n - 1. */
+void synth_batch_params(int32_t g, uint64_t seed, int32_t nmin, int32_t nmax, double dmin, double dmax,
+                        int32_t* n, int32_t* kind, double* deg) {
+    sm64 r = sm64_stream(seed, (uint64_t)g);
+    double u = sm64_unif(&r);
+    int32_t nn = (int32_t)floor(exp(log((double)nmin) + u * (log((double)nmax + 1.0) - log((double)nmin))));
+    if (nn < nmin) nn = nmin;
+    if (nn > nmax) nn = nmax;
+    *n = nn;
+    *kind = (int32_t)(sm64_next(&r) & 1u);
+    double d = dmin + sm64_unif(&r) * (dmax - dmin);
+    if (d > nn - 1) d = nn - 1;
+    *deg = d;
+}
+
+/* Pairs of one batch graph (local ids).  Chung-Lu weights follow a power law
+ * w^(-gamma) with the given mean, capped at sqrt(n * mean) (so that
+ * w_u w_v <= sum w). */
+static int64_t batch_graph_pairs(int32_t g, uint64_t seed, int32_t n, int32_t kind, double deg, double gamma,
+                                 int32_t** out) {
+    uint64_t gs = seed * 1000003ULL + (uint64_t)g * 7919ULL + 17ULL;
+    if (kind == 0 || n < 3) return synth_er(n, n > 1 ? deg / (n - 1) : 0.0, gs, out);
+    double wmax = sqrt((double)n * deg);
+    if (wmax > n - 1) wmax = n - 1;
+    /* x_min by bisection on the truncated power-law mean */
+    double lo = 1e-6, hi = deg;
+    for (int it = 0; it < 200; it++) {
+        double xm = 0.5 * (lo + hi);
+        double a = 1.0 - gamma, b = 2.0 - gamma;
+        double norm = (pow(wmax, a) - pow(xm, a)) / a;
+        double first = (pow(wmax, b) - pow(xm, b)) / b;
+        if (first / norm < deg) lo = xm; else hi = xm;
+    }
+    double* w = (double*)malloc((size_t)n * sizeof(double));
+    if (!w) return -1;
+    synth_powerlaw_weights(n, gamma, 0.5 * (lo + hi), wmax, gs, w);
+    int64_t c = synth_chung_lu(n, w, gs, out);
+    free(w);
+    return c;
+}
+
+/* Total vertex count of a batch (to size buffers). */
+int64_t synth_batch_vertices(int32_t ngraphs, uint64_t seed, int32_t nmin, int32_t nmax, double dmin, double dmax) {
+    int64_t tot = 0;
+    for (int32_t g = 0; g < ngraphs; g++) {
+        int32_t n, kind;
+        double d;
+        synth_batch_params(g, seed, nmin, nmax, dmin, dmax, &n, &kind, &d);
+        tot += n;
+    }
+    return tot;
+}
+
+/* Build the packed CSR of a batch: voff[ngraphs+1] (vertex offsets), row_ptr[N+1]
+ * (global offsets, int64), and a malloc'd col array (global ids) in *col_out.
+ * Returns the entry count (nnz) or -1. */
+int64_t synth_batch(int32_t ngraphs, uint64_t seed, int32_t nmin, int32_t nmax, double dmin, double dmax,
+                    double gamma, int32_t* voff, int64_t* row_ptr, int32_t** col_out) {
+    *col_out = NULL;
+    int64_t V = 0;
+    voff[0] = 0;
+    for (int32_t g = 0; g < ngraphs; g++) {
+        int32_t n, kind;
+        double d;
+        synth_batch_params(g, seed, nmin, nmax, dmin, dmax, &n, &kind, &d);
+        V += n;
+        voff[g + 1] = (int32_t)V;
+    }
+    int64_t cap = 1 << 20, nnz = 0;
+    int32_t* col = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+    int64_t* deg = (int64_t*)calloc((size_t)(V + 1), sizeof(int64_t));
+    if (!col || !deg) { free(col); free(deg); return -1; }
+    row_ptr[0] = 0;
+    for (int32_t g = 0; g < ngraphs; g++) {
+        int32_t n = voff[g + 1] - voff[g], kind;
+        double d;
+        synth_batch_params(g, seed, nmin, nmax, dmin, dmax, &n, &kind, &d);
+        int32_t* pairs = NULL;
+        int64_t np = batch_graph_pairs(g, seed, n, kind, d, gamma, &pairs);
+        if (np < 0) { free(col); free(deg); return -1; }
+        int32_t base = voff[g];
+        for (int32_t v = 0; v < n; v++) deg[base + v] = 0;
+        for (int64_t e = 0; e < np; e++) { deg[base + pairs[2 * e]]++; deg[base + pairs[2 * e + 1]]++; }
+        int64_t need = nnz + 2 * np;
+        if (need > cap) {
+            while (cap < need) cap *= 2;
+            int32_t* q = (int32_t*)realloc(col, (size_t)cap * sizeof(int32_t));
+            if (!q) { free(pairs); free(col); free(deg); return -1; }
+            col = q;
+        }
+        /* offsets of this graph's rows, then scatter both directions */
+        for (int32_t v = 0; v < n; v++) row_ptr[base + v + 1] = row_ptr[base + v] + deg[base + v];
+        for (int32_t v = 0; v < n; v++) deg[base + v] = row_ptr[base + v];
+        for (int64_t e = 0; e < np; e++) {
+            int32_t a = pairs[2 * e], b = pairs[2 * e + 1];
+            col[deg[base + a]++] = base + b;
+            col[deg[base + b]++] = base + a;
+        }
+        for (int32_t v = 0; v < n; v++) sort_row(col + row_ptr[base + v], row_ptr[base + v + 1] - row_ptr[base + v]);
+        nnz = need;
+        free(pairs);
+    }
+    free(deg);
+    *col_out = col;
+    return nnz;
+}

@@ -56,12 +56,14 @@ def test_counts_match_oracle(kc, cache, name, scheme):
             assert got == want[k], (name, order, scheme, k)
 
 
-@pytest.mark.parametrize("width", [1, 2, 4, 8, 16, 32])
+@pytest.mark.parametrize("width", [0, 1, 2, 4, 8, 16, 32])
 def test_widths_agree(kc, cache, width):
+    # width 0/1: lane walks (pair tasks and helping at k >= 6 VC / 7 EC on wide roots);
+    # 2..32: sub-wavefront groups
     g, d = get(cache, kc, "heavy_core", kc.ORDER_DEGENERACY)
-    want = oracle_counts(g, (4, 6))
+    want = oracle_counts(g, (4, 6, 7))
     for scheme in (1, 2):
-        for k in (4, 6):
+        for k in (4, 6, 7):
             assert kc.count(d, k, scheme=scheme, width=width) == want[k], (width, scheme, k)
 
 
