@@ -70,6 +70,156 @@ def cpu_baseline(g, ks, frac, seed=0):
     }
 
 
+def bench_batched(kc, ngraphs, k, reps):
+    """Batched form vs plain per-graph launches on the batched workload: graphs/s,
+    per-graph counts compared exactly."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2104_13209_amd import autotune
+    t0 = time.perf_counter()
+    b = synth.batch(ngraphs, seed=4)
+    log("batch: %d graphs, %d vertices, %d edges (%.1f s)" % (b.ngraphs, b.n, b.nnz // 2, time.perf_counter() - t0))
+    bd = kc.batch_to_device(b)
+    plan, report = autotune.tune(b, k)
+    log("autotuned plan: %s" % report)
+    bg = kc.BatchGraph(bd, k, plan)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(reps):
+        bg.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    gpu_ms = e0.elapsed_time(e1) / reps
+    batched = bg.counts()
+    # plain: one kc_orient + kc_count per graph, each on its own device CSR
+    dev = bd.row_ptr.device
+    graphs = [kc.to_device(b.graph(g), dev) for g in range(b.ngraphs)]
+    nmax = max(g.n for g in graphs)
+    nnzmax = max(g.nnz for g in graphs)
+    ows = torch.empty(kc.orient_workspace_bytes(nmax, nnzmax, kc.ORDER_DEGREE), dtype=torch.uint8, device=dev)
+    dag = kc.Dag(nmax, nnzmax // 2, 0, -1, 0, torch.empty(nmax + 1, dtype=torch.int32, device=dev),
+                 torch.empty(max(nnzmax // 2, 1), dtype=torch.int32, device=dev),
+                 torch.empty(max(nnzmax // 2, 1), dtype=torch.int32, device=dev),
+                 torch.empty(nmax, dtype=torch.int32, device=dev))
+    probe = kc.Dag(nmax, nnzmax // 2, 1024, -1, 0, dag.row_ptr, dag.col, dag.src, dag.perm)
+    cws = torch.empty(kc.count_workspace_bytes(probe, k, False), dtype=torch.uint8, device=dev)
+    plain = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in graphs:
+        d = kc.orient(g, kc.ORDER_DEGREE, validate=False, ws=ows, out=dag)
+        plain.append(kc.count(d, k, ws=cws))
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    mism = sum(1 for x, y in zip(batched, plain) if x != y)
+    return {
+        "workload": "%d graphs, n log-uniform [50, 5000], ER / Chung-Lu(2.3) 50/50, mean degree U[8, 64], "
+                    "seed 4 (%d vertices, %d edges)" % (b.ngraphs, b.n, b.nnz // 2),
+        "k": k,
+        "graphs_per_s": b.ngraphs / wall,
+        "ms_per_batch": round(wall * 1e3, 3),
+        "gpu_ms_per_batch": round(gpu_ms, 3),
+        "plain_graphs_per_s": b.ngraphs / plain_s,
+        "plain_s": round(plain_s, 3),
+        "speedup_vs_plain": round(plain_s / wall, 2),
+        "mismatches_vs_plain": mism,
+        "total_cliques": str(sum(batched)),
+        "plan": report,
+        "hipgraph": True,
+    }
+
+
+def served_pool(ngraphs, nmin, nmax, seed=5):
+    """Pool of graphs for serving: shapes uniform over {power-law Chung-Lu
+    (gamma 2.1, mean 32, w_max = sqrt(sum w)), dense core (Chung-Lu background +
+    planted communities of 20-60 at density 0.8), Erdos-Renyi / Chung-Lu(2.3) with
+    mean degree U[8, 64]}, vertex counts log-uniform on [nmin, nmax]."""
+    import synth
+    graphs, kinds = [], []
+    for i in range(ngraphs):
+        u = synth.uniform(seed, 3 * i)
+        n = int(math.exp(math.log(nmin) + u * (math.log(nmax) - math.log(nmin))))
+        kind = int(synth.uniform(seed, 3 * i + 1) * 3)
+        gs = seed * 100003 + i
+        if kind == 0:
+            g = synth.chung_lu(n, 2.1, 32.0, math.sqrt(32.0 * n), gs)
+        elif kind == 1:
+            g = synth.dense_core(n, 10.0, 2.1, max(1, n // 5000), 20, 60, 0.8, gs)
+        else:
+            d = 8.0 + 56.0 * synth.uniform(seed, 3 * i + 2)
+            if synth.uniform(seed, 3 * i + 2 + 7919) < 0.5:
+                g = synth.erdos_renyi(n, d / (n - 1), gs)
+            else:
+                g = synth.chung_lu(n, 2.3, d, math.sqrt(d * n), gs)
+        graphs.append(g)
+        kinds.append(kind)
+    return graphs, kinds
+
+
+def percentile(xs, q):
+    ys = sorted(xs)
+    if not ys:
+        return None
+    i = min(len(ys) - 1, max(0, int(math.ceil(q / 100.0 * len(ys))) - 1))
+    return ys[i]
+
+
+def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, seed=5):
+    """Continuous batching (kc_server, `slots` workers) vs sequential launches
+    (one worker) on the same Poisson trace of (graph, k, pivot) queries."""
+    import numpy as np
+    t0 = time.perf_counter()
+    graphs, kinds = served_pool(ngraphs, nmin, nmax, seed)
+    log("served pool: %d graphs, %d edges (%.1f s)" % (len(graphs), sum(g.m for g in graphs), time.perf_counter() - t0))
+    dags = [kc.orient(kc.to_device(g), kc.ORDER_DEGENERACY, validate=False) for g in graphs]
+    rng = np.random.default_rng(seed)
+    total = nwarm + nq
+    qs = [(int(rng.integers(0, ngraphs)), int(rng.integers(3, 13)), bool(rng.random() < 0.3)) for _ in range(total)]
+    budget = int(budget_gb * (1 << 30))
+    # service rate of sequential launches, measured back to back on the warm-up queries
+    with kc.Server(dags, slots=1, mem_budget=budget) as sv:
+        t0 = time.perf_counter()
+        res = kc.replay_trace(sv, [(0.0, g, k, p) for g, k, p in qs[:nwarm]])
+        seq_rate = nwarm / (time.perf_counter() - t0)
+    lam = util * seq_rate
+    gaps = rng.exponential(1.0 / lam, size=nq)
+    arr = np.cumsum(gaps) - gaps[0]
+    trace = [(float(a), g, k, p) for a, (g, k, p) in zip(arr, qs[nwarm:])]
+    out = {}
+    for name, nslots in (("served", slots), ("sequential", 1)):
+        with kc.Server(dags, slots=nslots, mem_budget=budget) as sv:
+            t0 = time.perf_counter()
+            rs = kc.replay_trace(sv, trace)
+            span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
+        lat = [r.latency * 1e3 for r in rs]
+        out[name] = {"slots": nslots, "queries_per_s": len(rs) / span, "p50_ms": round(percentile(lat, 50), 3),
+                     "p99_ms": round(percentile(lat, 99), 3), "mean_ms": round(sum(lat) / len(lat), 3),
+                     "refused": sum(1 for r in rs if r.status == kc.ENOMEM),
+                     "errors": sum(1 for r in rs if r.status not in (kc.OK, kc.ENOMEM))}
+        out[name + "_results"] = [(r.status, r.value) for r in rs]
+    same = out.pop("served_results") == out.pop("sequential_results")
+    # saturation: every query submitted at once (closed loop), throughput only
+    for name, nslots in (("served_saturated", slots), ("sequential_saturated", 1)):
+        with kc.Server(dags, slots=nslots, mem_budget=budget) as sv:
+            rs = kc.replay_trace(sv, [(0.0, g, k, p) for _, g, k, p in trace])
+            span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
+        out[name] = {"queries_per_s": len(rs) / span}
+    out.update({
+        "workload": "%d graphs (n log-uniform [%d, %d], shapes power-law / dense-core / batch-like), %d queries "
+                    "after %d warm-up, k U{3..12}, pivot p=0.3, Poisson arrivals at %.2f x the sequential service rate"
+                    % (ngraphs, nmin, nmax, nq, nwarm, util),
+        "arrival_rate_qps": lam,
+        "sequential_service_qps": seq_rate,
+        "memory_budget_bytes": budget,
+        "results_identical": same,
+    })
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +232,19 @@ def main():
     ap.add_argument("--scheme", type=int, default=2)
     ap.add_argument("--cpu-frac", type=float, default=0.005)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=10000)
+    ap.add_argument("--batch-k", type=int, default=5)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-graphs", type=int, default=200)
+    ap.add_argument("--serve-nmin", type=int, default=10000)
+    ap.add_argument("--serve-nmax", type=int, default=100000)
+    ap.add_argument("--serve-queries", type=int, default=600)
+    ap.add_argument("--serve-warmup", type=int, default=60)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-util", type=float, default=0.7)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -172,6 +335,19 @@ def main():
                 % (sp.nodes[li], sp.word_ops[li], dom_ms),
     }
 
+    batched = None
+    if not args.no_batch:
+        log("batched form ...")
+        batched = bench_batched(kc, args.batch_graphs, args.batch_k, args.batch_reps)
+        log("batched: %.0f graphs/s vs plain %.0f graphs/s" % (batched["graphs_per_s"], batched["plain_graphs_per_s"]))
+
+    served = None
+    if not args.no_serve:
+        log("served form ...")
+        served = bench_served(kc, args.serve_graphs, args.serve_nmin, args.serve_nmax, args.serve_queries,
+                              args.serve_warmup, args.serve_slots, args.serve_budget_gb, args.serve_util)
+        log("served: %s" % {k: v for k, v in served.items() if k in ("served", "sequential")})
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle, sampled) ...")
@@ -201,6 +377,8 @@ def main():
         "per_k": per_k,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(res), flush=True)
 

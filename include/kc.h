@@ -198,6 +198,41 @@ KC_API size_t kc_batch_workspace(const kc_batch* b, int32_t k);
 KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t* counts, void* ws, size_t ws_bytes,
                               const kc_batch_plan* plan, void* stream);
 
+/* ------------------------------------------------------------- serving */
+
+/* A query server over oriented graphs that stay resident on the device
+ * (continuous batching).  Queries (graph, k, pivot) are admitted in arrival
+ * order when one of `slots` workers is free and the query's workspace
+ * (kc_count_workspace) fits in the server's device arena of `mem_budget` bytes;
+ * admitted queries run concurrently, one HIP stream per worker, so work of
+ * queries that arrive while others run overlaps on the device.  A query that
+ * could never fit the arena completes at once with status KC_ENOMEM.
+ * Ownership: the server allocates its arena and streams in kc_server_create and
+ * frees them in kc_server_destroy (the only entry points that allocate device
+ * memory); the kc_dag arrays stay owned by the caller and must outlive the
+ * server.  Thread-safe: submit and wait may be called from any host thread. */
+typedef struct kc_server kc_server;
+
+typedef struct kc_query_result {
+    uint64_t ticket;
+    int32_t graph, k, pivot;
+    int32_t status;            /* kc_count's status for this query            */
+    kc_u128 count;
+    double t_submit;           /* host steady-clock seconds                   */
+    double t_start;            /* admitted and started on a worker            */
+    double t_done;             /* result on the host                          */
+    uint64_t workspace;        /* bytes admitted against the arena            */
+} kc_query_result;
+
+KC_API int32_t kc_server_create(const kc_dag* dags, int32_t ndags, int32_t slots, uint64_t mem_budget,
+                                kc_server** out);
+/* Enqueue a query; *ticket identifies it.  Never blocks on the device. */
+KC_API int32_t kc_server_submit(kc_server* s, int32_t graph, int32_t k, int32_t pivot, uint64_t* ticket);
+/* Block until the query is done and return its result (each ticket once). */
+KC_API int32_t kc_server_wait(kc_server* s, uint64_t ticket, kc_query_result* res);
+/* Finish admitted queries, drop queries never admitted, free the server. */
+KC_API int32_t kc_server_destroy(kc_server* s);
+
 /* Static text for a status code. */
 KC_API const char* kc_strerror(int32_t status);
 

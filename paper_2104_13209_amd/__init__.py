@@ -380,3 +380,99 @@ class BatchGraph:
     def counts(self):
         torch.cuda.synchronize()
         return counts_from_device(self.out)
+
+
+# ---------------------------------------------------------------- serving
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("graph", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("pivot", ctypes.c_int32), ("status", ctypes.c_int32), ("count", _U128),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("workspace", ctypes.c_uint64)]
+
+    @property
+    def value(self) -> int:
+        return int(self.count.lo) | (int(self.count.hi) << 64)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_submit
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_ready", False):
+        L.kc_server_create.argtypes = [ctypes.POINTER(_Dag), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.kc_server_create.restype = ctypes.c_int32
+        L.kc_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.kc_server_submit.restype = ctypes.c_int32
+        L.kc_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(QueryResult)]
+        L.kc_server_wait.restype = ctypes.c_int32
+        L.kc_server_destroy.argtypes = [ctypes.c_void_p]
+        L.kc_server_destroy.restype = ctypes.c_int32
+        L._server_ready = True
+    return L
+
+
+class Server:
+    """kc_server: continuous batching of count queries over resident DAGs."""
+
+    def __init__(self, dags, slots: int = 4, mem_budget: int = 8 << 30):
+        L = _server_lib()
+        self._dags = list(dags)          # keep the device tensors alive
+        arr = (_Dag * len(self._dags))(*[d._c() for d in self._dags])
+        self._arr = arr
+        h = ctypes.c_void_p()
+        st = L.kc_server_create(arr, len(self._dags), slots, mem_budget, ctypes.byref(h))
+        if st != OK:
+            raise KcError(st, "kc_server_create")
+        self._h = h
+
+    def submit(self, graph: int, k: int, pivot: bool = False) -> int:
+        t = ctypes.c_uint64(0)
+        st = _server_lib().kc_server_submit(self._h, graph, k, int(bool(pivot)), ctypes.byref(t))
+        if st != OK:
+            raise KcError(st, "kc_server_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int) -> QueryResult:
+        r = QueryResult()
+        st = _server_lib().kc_server_wait(self._h, ticket, ctypes.byref(r))
+        if st != OK:
+            raise KcError(st, "kc_server_wait")
+        return r
+
+    def close(self):
+        if self._h:
+            _server_lib().kc_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def replay_trace(server: Server, trace):
+    """Submit (t_arrival_s, graph, k, pivot) queries at their arrival offsets from
+    now (open loop) and return the results in submission order."""
+    import time
+    t0 = time.perf_counter()
+    tickets = []
+    for t_arr, g, k, piv in trace:
+        while True:
+            dt = t_arr - (time.perf_counter() - t0)
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.002) if dt > 0.0005 else 0)
+        tickets.append(server.submit(g, k, piv))
+    return [server.wait(t) for t in tickets]
