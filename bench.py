@@ -308,31 +308,38 @@ def main():
         ms = sum(p.ms_total for p in ps) / len(ps)
         ml = sum(p.ms_light for p in ps) / len(ps)
         mh = sum(p.ms_heavy for p in ps) / len(ps)
+        mw = [sum(p.ms_width[j] for p in ps) / len(ps) for j in range(6)]
         per_k[str(k)] = {"count": str(counts[k]), "count_ms": round(ms, 3), "edges_per_s": m / (ms / 1e3),
+                         "classify_ms": round(sum(p.ms_classify for p in ps) / len(ps), 3),
                          "light_ms": round(ml, 3), "heavy_ms": round(mh, 3),
-                         "light_roots": ps[0].light_roots, "heavy_roots": ps[0].heavy_roots}
-        phases.append((ml, k, "light"))
-        phases.append((mh, k, "heavy"))
+                         "width_list_ms": [round(x, 3) for x in mw],
+                         "width_list_roots": [int(ps[0].roots_width[j]) for j in range(6)]}
+        for j in range(6):
+            phases.append((mw[j], k, j))
 
-    # dominant kernel and its algorithmic work (separate, untimed stats pass)
-    dom_ms, dom_k, dom_list = max(phases)
+    # dominant kernel launch (one width list at one k) and its algorithmic work,
+    # from a separate, untimed stats pass of the same call
+    dom_ms, dom_k, dom_j = max(phases)
     sp = kc.Profile()
     c_stats = kc.count(dag, dom_k, scheme=args.scheme, width=args.width, ws=cws, profile=sp, collect_stats=True)
     assert c_stats == counts[dom_k]
-    li = 0 if dom_list == "light" else 1
-    work_ops = 2.0 * sp.word_ops[li]
+    work_ops = 2.0 * sp.words_width[dom_j]
     achieved = work_ops / (dom_ms / 1e3) / 1e12
     roofline = {
         "bound": "alu",
-        "kernel": "k_go (%s list, k=%d)" % (dom_list, dom_k),
+        "kernel": "k_lane<MAXW=%d, %s> (width list %d, k=%d)" % (1 << dom_j, "EC" if args.scheme == 2 else "VC",
+                                                               dom_j, dom_k),
         "achieved": round(achieved, 4),
         "peak": round(VALU_PEAK_TOPS, 2),
         "unit": "TOP/s",
         "frac": round(achieved / VALU_PEAK_TOPS, 5),
         "traffic": None,
         "work": "2 int32 ops (AND + popcount) per bitset word per expanded tree node: "
-                "%d nodes, %d words in one launch of %.3f ms (HIP events, mean of timed steps)"
-                % (sp.nodes[li], sp.word_ops[li], dom_ms),
+                "%d nodes x %d-word rows = %d words in one launch of %.3f ms (HIP events, mean of timed steps)"
+                % (sp.nodes_width[dom_j], 1 << dom_j, sp.words_width[dom_j], dom_ms),
+        "lane_utilisation": round(sp.nodes_width[dom_j] / max(1, 64 * sp.iters_width[dom_j]), 4),
+        "wavefront_busy_fraction": round(float(sp.busy_width[dom_j]), 4),
+        "wavefronts": int(sp.waves_width[dom_j]),
     }
 
     batched = None

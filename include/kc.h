@@ -103,6 +103,16 @@ typedef struct kc_profile {
     uint64_t word_ops[2];
     int32_t light_roots;       /* roots in each list (after pruning)            */
     int32_t heavy_roots;
+    /* Default (lane-walk) path only: per width list j (rows of 2^j words),
+     * the launch duration, roots, expanded nodes and their bitset words. */
+    float ms_width[6];
+    int32_t roots_width[6];
+    uint64_t nodes_width[6];
+    uint64_t words_width[6];
+    uint64_t iters_width[6];   /* wavefront loop iterations (lane utilisation =
+                                  nodes / (64 x iterations))                    */
+    int32_t waves_width[6];    /* wavefronts launched                           */
+    float busy_width[6];       /* mean wavefront busy time / launch span         */
 } kc_profile;
 
 /* Tuning options; NULL means defaults.  scheme: KC_SCHEME_*; width: lanes per

@@ -55,7 +55,11 @@ class Profile(ctypes.Structure):
     _fields_ = [("ms_classify", ctypes.c_float), ("ms_light", ctypes.c_float),
                 ("ms_heavy", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("nodes", ctypes.c_uint64 * 2), ("word_ops", ctypes.c_uint64 * 2),
-                ("light_roots", ctypes.c_int32), ("heavy_roots", ctypes.c_int32)]
+                ("light_roots", ctypes.c_int32), ("heavy_roots", ctypes.c_int32),
+                ("ms_width", ctypes.c_float * 6), ("roots_width", ctypes.c_int32 * 6),
+                ("nodes_width", ctypes.c_uint64 * 6), ("words_width", ctypes.c_uint64 * 6),
+                ("iters_width", ctypes.c_uint64 * 6), ("waves_width", ctypes.c_int32 * 6),
+                ("busy_width", ctypes.c_float * 6)]
 
 
 class _Opts(ctypes.Structure):

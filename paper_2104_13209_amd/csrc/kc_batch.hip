@@ -148,7 +148,7 @@ BatchWs carve_batch(void* ws, const kc_batch* b, size_t* bytes) {
     w.task_tot = c.take<int>(static_cast<size_t>(nr));
     w.nactive = device_cus() * kLaneWavesPerCU;
     w.active = c.take<int>(static_cast<size_t>(w.nactive));
-    w.acc = c.take<unsigned long long>(8);
+    w.acc = c.take<unsigned long long>(kAccWords);
     *bytes = c.bytes();
     return w;
 }
@@ -210,7 +210,7 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
     k_gid<<<grid_for(n), kBlock, 0, s>>>(n, w.perm, b->voff, G, w.gid);
     k_graph_scheme<<<grid_for(G), kBlock, 0, s>>>(G, b->voff, pl, w.scheme);
     k_fill_i32<<<grid_for(w.nactive), kBlock, 0, s>>>(w.active, -1, w.nactive);
-    k_fill_u64<<<1, kBlock, 0, s>>>(w.acc, 0ull, 8);
+    k_fill_u64<<<1, kBlock, 0, s>>>(w.acc, 0ull, kAccWords);
     KC_CHECK(hipGetLastError());
     if (m == 0) return KC_OK;
 
@@ -246,7 +246,7 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
             LaneLaunch L;
             L.k = k;
             L.ec = ec;
-            L.pair = deep && lst >= 2;
+            L.pair = deep && lst >= 1;
             L.stats = false;
             L.maxw = 1 << lst;
             L.list = lst;
@@ -261,6 +261,7 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
             L.active = w.active;
             L.acc = w.acc;
             L.stats_ptr = w.acc + 2;
+            L.iters_ptr = w.acc + 4;
             L.gacc = reinterpret_cast<unsigned long long*>(counts);
             L.gid = w.gid;
             st = lane_launch(L, s);

@@ -388,6 +388,7 @@ int launch_heavy(const GoParams& P, int width, int d_max, bool st, hipStream_t s
 // HIP events for kc_profile, created on first use (one set per process).
 struct ProfileEvents {
     hipEvent_t ev[4];
+    hipEvent_t wl[2 * kWidthLists];    // start / end of each width-list launch
     bool ready = false;
 };
 
@@ -395,6 +396,7 @@ int profile_events(ProfileEvents** out) {
     static ProfileEvents pe;
     if (!pe.ready) {
         for (int i = 0; i < 4; i++) KC_CHECK(hipEventCreate(&pe.ev[i]));
+        for (int i = 0; i < 2 * kWidthLists; i++) KC_CHECK(hipEventCreate(&pe.wl[i]));
         pe.ready = true;
     }
     *out = &pe;
@@ -427,7 +429,7 @@ int pick_width(const kc_opts* o, int d_max, bool light) {
 // the results back.  `pivot_all` selects the pivot kernels (-1: graph
 // orientation, 0: pivot with target k, 1: pivot count-all).
 int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const CountWs& w, bool ec,
-              unsigned long long preload, unsigned long long res[8], int hctl[CC_WORDS],
+              unsigned long long preload, unsigned long long res[kAccWords], int hctl[CC_WORDS],
               unsigned long long* counts_out, int counts_len, hipStream_t s) {
     kc_profile* prof = o ? o->profile : nullptr;
     const bool stats = o && o->collect_stats;
@@ -439,7 +441,9 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     }
     const int nroots = ec ? d->m : d->n;
     KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
-    unsigned long long init[8] = {preload, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    unsigned long long init[kAccWords] = {};
+    init[0] = preload;
+    for (int j = 0; j < kWidthLists; j++) init[6 + 3 * kWidthLists + 3 * j + 1] = ~0ull;   // min start
     KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
     if (pivot_all >= 0) {
         KC_CHECK(hipMemsetAsync(w.counts, 0, 2 * sizeof(unsigned long long) * (w.binom_n + 1), s));
@@ -458,7 +462,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         int top = 0;
         while (top < kWidthLists - 1 && (32 << top) < d->d_max) top++;
         const bool deep = k >= (ec ? 3 : 2) + 4;
-        if (lane_lds_bytes(1 << top, k, ec, deep && top >= 2) > 160 * 1024) lane_path = false;
+        if (lane_lds_bytes(1 << top, k, ec, deep && top >= 1) > 160 * 1024) lane_path = false;
     }
     if (lane_path) {
         KC_CHECK(hipMemsetAsync(w.active, 0xff, sizeof(int) * w.nactive, s));
@@ -479,6 +483,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     if (prof && !lane_path) KC_CHECK(hipEventRecord(pe->ev[1], s));
 
     int st = KC_OK;
+    int lane_grid[kWidthLists] = {0, 0, 0, 0, 0, 0};
     if (lane_path) {
         // lane walks over the width lists, widest first so that the largest roots
         // start early; profile: heavy = lists with >= 4 words, light = 1-2 words
@@ -497,7 +502,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             LaneLaunch L;
             L.k = k;
             L.ec = ec;
-            L.pair = deep && lst >= 2;
+            L.pair = deep && lst >= 1;
             L.stats = stats;
             L.maxw = 1 << lst;
             L.list = lst;
@@ -511,11 +516,21 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.task_tot = w.task_tot;
             L.active = w.active;
             L.acc = w.acc;
-            L.stats_ptr = w.acc + (lst >= 2 ? 4 : 2);
+            L.stats_ptr = w.acc + 6 + 2 * lst;
+            L.iters_ptr = w.acc + 6 + 2 * kWidthLists + lst;
+            L.timing_ptr = w.acc + 6 + 3 * kWidthLists + 3 * lst;
+            if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst], s));
+            L.grid_out = &lane_grid[lst];
             st = lane_launch(L, s);
             if (st != KC_OK) return st;
+            if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst + 1], s));
         }
         if (prof && top < 1) KC_CHECK(hipEventRecord(pe->ev[2], s));
+        if (prof)
+            for (int lst = top + 1; lst < kWidthLists; lst++) {   // unlaunched lists: zero-length spans
+                KC_CHECK(hipEventRecord(pe->wl[2 * lst], s));
+                KC_CHECK(hipEventRecord(pe->wl[2 * lst + 1], s));
+            }
     } else if (pivot_all < 0) {
         GoParams P;
         P.n = d->n;
@@ -569,7 +584,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         if (!lane_path && d->d_max <= kLightCap) KC_CHECK(hipEventRecord(pe->ev[2], s));
         KC_CHECK(hipEventRecord(pe->ev[3], s));
     }
-    KC_CHECK(hipMemcpyAsync(res, w.acc, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipMemcpyAsync(res, w.acc, kAccWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     KC_CHECK(hipMemcpyAsync(hctl, w.ctl, CC_WORDS * sizeof(int), hipMemcpyDeviceToHost, s));
     if (counts_out)
         KC_CHECK(hipMemcpyAsync(counts_out, w.counts, 2 * sizeof(unsigned long long) * counts_len,
@@ -589,10 +604,34 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             prof->nodes[i] = stats ? res[2 + 2 * i] : 0;
             prof->word_ops[i] = stats ? res[3 + 2 * i] : 0;
         }
+        for (int j = 0; j < kWidthLists; j++) {
+            prof->ms_width[j] = 0.f;
+            prof->roots_width[j] = lane_path ? hctl[CC_WN0 + j] : 0;
+            prof->waves_width[j] = lane_path ? lane_grid[j] : 0;
+            prof->nodes_width[j] = lane_path && stats ? res[6 + 2 * j] : 0;
+            prof->words_width[j] = lane_path && stats ? res[7 + 2 * j] : 0;
+            prof->iters_width[j] = lane_path && stats ? res[6 + 2 * kWidthLists + j] : 0;
+            {
+                const unsigned long long* tm = res + 6 + 3 * kWidthLists + 3 * j;
+                const double span = tm[2] > tm[1] && tm[1] != ~0ull ? static_cast<double>(tm[2] - tm[1]) : 0.0;
+                prof->busy_width[j] = lane_path && stats && span > 0 && prof->waves_width[j] > 0
+                                          ? static_cast<float>(static_cast<double>(tm[0]) / (span * prof->waves_width[j]))
+                                          : 0.f;
+            }
+            if (lane_path) KC_CHECK(hipEventElapsedTime(&prof->ms_width[j], pe->wl[2 * j], pe->wl[2 * j + 1]));
+        }
         if (lane_path) {
             prof->light_roots = hctl[CC_WN0] + hctl[CC_WN0 + 1];
             prof->heavy_roots = 0;
             for (int j = 2; j < kWidthLists; j++) prof->heavy_roots += hctl[CC_WN0 + j];
+            for (int i = 0; i < 2; i++) {
+                prof->nodes[i] = 0;
+                prof->word_ops[i] = 0;
+            }
+            for (int j = 0; j < kWidthLists; j++) {
+                prof->nodes[j >= 2] += prof->nodes_width[j];
+                prof->word_ops[j >= 2] += prof->words_width[j];
+            }
         } else {
             prof->light_roots = hctl[CC_LIGHT_N];
             prof->heavy_roots = hctl[CC_HEAVY_N];
@@ -639,7 +678,7 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     }
     const int scheme = pick_scheme(o, k);
     if (scheme != KC_SCHEME_VC && scheme != KC_SCHEME_EC) return KC_EINVAL;
-    unsigned long long res[8];
+    unsigned long long res[kAccWords];
     int hctl[CC_WORDS];
     int st = run_count(d, k, pivot ? 0 : -1, o, w, scheme == KC_SCHEME_EC, preload, res, hctl, nullptr, 0, s);
     if (st != KC_OK) return st;
@@ -668,7 +707,7 @@ extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* 
         const int len = w.binom_n + 1;
         unsigned long long* host = new (std::nothrow) unsigned long long[2 * static_cast<size_t>(len)];
         if (!host) return KC_ENOMEM;
-        unsigned long long res[8];
+        unsigned long long res[kAccWords];
         int hctl[CC_WORDS];
         int st = run_count(d, 0, 1, o, w, scheme == KC_SCHEME_EC, 0ull, res, hctl, host, len, s);
         if (st != KC_OK) { delete[] host; return st; }

@@ -9,6 +9,7 @@ constexpr int kLightCap = 64;          // |S| bound of the light root list
 constexpr int kPivBlocksPerCU = 8;     // grid cap of the heavy pivot kernel (sizes its stacks)
 constexpr int kLaneWavesPerCU = 32;    // grid cap of the lane-walk kernel (sizes its registry)
 constexpr int kWidthLists = 6;         // root lists by bitset words per row: 1, 2, 4, 8, 16, 32
+constexpr int kAccWords = 6 + 6 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, busy, start, end
 
 enum CountCtl {
     CC_LIGHT_N = 0,      // light root count
@@ -23,9 +24,11 @@ enum CountCtl {
 };
 
 // Saved levels a depth-first walk starting at path length `first` may need:
-// levels are saved only while the path is shorter than k - 2.
+// the last two levels of a path are counted in registers (a node one level
+// above the leaves adds the edge count of its candidate set), so levels are
+// saved only while the path is shorter than k - 3.
 inline int k_levels(int k, int first) {
-    const int lv = k - 2 - first;
+    const int lv = k - 3 - first;
     return lv < 1 ? 1 : lv;
 }
 
@@ -47,7 +50,7 @@ inline int piv_level_words(int maxw) { return 3 * maxw + 4; }
 
 struct CountWs {
     int* ctl;
-    unsigned long long* acc;      // [lo, hi, light nodes, light words, heavy nodes, heavy words]
+    unsigned long long* acc;      // [lo, hi, light nodes, words, heavy nodes, words, then per width list nodes, words]
     int* light;
     int* heavy;
     unsigned long long* counts;   // count_all: (binom_n + 1) x {lo, hi}
@@ -68,7 +71,7 @@ inline CountWs carve_count(void* ws, const kc_dag* d, bool pivot, size_t* bytes)
     CountWs w{};
     const int nr = d->m > d->n ? d->m : d->n;
     w.ctl = c.take<int>(CC_WORDS);
-    w.acc = c.take<unsigned long long>(8);
+    w.acc = c.take<unsigned long long>(kAccWords);
     w.light = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
     w.heavy = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
     w.task_ctr = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
@@ -128,6 +131,9 @@ struct LaneLaunch {
     int* active;
     unsigned long long* acc;
     unsigned long long* stats_ptr;
+    unsigned long long* iters_ptr = nullptr;
+    unsigned long long* timing_ptr = nullptr;
+    int* grid_out = nullptr;              // receives the launched grid (wavefronts)
     unsigned long long* gacc = nullptr;   // batched: per-graph counters
     const int* gid = nullptr;             // batched: graph of each DAG vertex
 };

@@ -27,6 +27,9 @@
 namespace kc {
 namespace {
 
+constexpr int kPairChunk = 64;    // pair tasks claimed per global atomic
+constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
+
 struct LaneParams {
     int k;
     int s_cap;
@@ -43,6 +46,8 @@ struct LaneParams {
     int* active;                    // pair mode: root slot owned by each wavefront, -1 if none
     unsigned long long* acc;        // [lo, hi]
     unsigned long long* stats;      // [nodes, words]
+    unsigned long long* iters;      // traversal loop iterations (per wavefront, summed)
+    unsigned long long* timing;     // [sum of wavefront busy ticks, min start, max end]
     unsigned long long* gacc;       // batched: per-graph {lo, hi}; null otherwise
     const int* __restrict__ gid;    // batched: graph of each DAG vertex
 };
@@ -72,6 +77,280 @@ __device__ __forceinline__ int select_bit(unsigned int x, int r) {
     return pos;
 }
 
+// Edges of the sub-graph induced by Y: sum over x in Y of |Y cap B[x]|.  Rows
+// are upper triangular, so this counts every pair once in any visiting order,
+// and row x (word t) can skip the words below t.  This is the whole last level
+// of Fig. 2 under a node whose candidate set is Y, done in one tight loop.
+template <int MAXW, int STRIDE>
+__device__ __forceinline__ unsigned int leaf_edges(const unsigned int (&Y)[MAXW], const unsigned int* B) {
+    unsigned int c = 0;
+#pragma unroll
+    for (int t = 0; t < MAXW; t++) {
+        unsigned int x = Y[t];
+        while (x) {
+            const int b = __ffs(x) - 1;
+            x &= x - 1u;
+            const unsigned int* row = B + (32 * t + b) * STRIDE;
+#pragma unroll
+            for (int w = t; w < MAXW; w++) c += __popc(Y[w] & row[w]);
+        }
+    }
+    return c;
+}
+
+// One root's traversal with rows of MW words (MW >= the root's word count):
+// bitset rows, pair-task prefix, then the lane walks until no lane holds work
+// and no task is left.  acc / nodes / wsum / iters accumulate per lane.
+template <int MW, bool EC, bool PAIR, bool STATS>
+__device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, int s, int slot, bool helping,
+                                          const int* S, unsigned int* B, int* pre, unsigned int* mbox,
+                                          unsigned int* stk, int* tctr, int* ttot, unsigned long long lt,
+                                          unsigned long long& acc, unsigned long long& nodes,
+                                          unsigned long long& wsum, unsigned long long& iters) {
+    constexpr int STRIDE = b_stride_of(MW);
+    constexpr int SLOT = MW + 1;                    // saved level: R words + p
+    const int lane = __lane_id();
+    extract_rows<1, false>(s, P.row_ptr, P.col, lane, S, B, STRIDE);
+    const unsigned long long W = static_cast<unsigned long long>((s + 31) >> 5);
+
+    int total = s;                                   // tasks of this root
+    if (PAIR) {
+        // pre[i] = number of pair tasks before row i
+        int run = 0;
+        for (int b0 = 0; b0 < s; b0 += 64) {
+            const int i = b0 + lane;
+            int c = 0;
+            if (i < s) {
+#pragma unroll
+                for (int t = 0; t < MW; t++) c += __popc(B[i * STRIDE + t]);
+            }
+            int inc = c;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += y;
+            }
+            if (i < s) pre[i] = run + inc - c;
+            run += __shfl(inc, 63);
+        }
+        if (lane == 0) pre[s] = run;
+        wave_sync_lds();
+        total = run;
+        if (!helping && lane == 0) {
+            __hip_atomic_store(&ttot[slot], run + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&P.active[blockIdx.x], slot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    // ---------------------------------------------------- traversal
+    unsigned int R[MW];
+#pragma unroll
+    for (int t = 0; t < MW; t++) R[t] = 0u;        // words >= Wr stay zero for this root
+    int p = 0, depth = 0, sbase = 0;
+    bool out = false;                                // no task left for this lane
+    int next_task = 0;                               // vertex tasks: wave counter
+    int tq = 0, tq_end = 0;                          // pair tasks: claimed, unassigned range
+    bool pq_done = false;                            // pair tasks: root counter exhausted
+
+    for (;;) {
+        if (STATS) iters += 1;
+        bool emp = true;
+#pragma unroll
+        for (int t = 0; t < MW; t++) emp &= R[t] == 0u;
+        // pop a saved level
+        if (emp && depth > sbase) {
+            depth--;
+            const unsigned int* f = stk + depth * SLOT * 64 + lane;
+#pragma unroll
+            for (int t = 0; t < MW; t++) R[t] = f[t * 64];
+            p = static_cast<int>(f[MW * 64]);
+            emp = false;
+        }
+        // claim tasks for lanes that have nothing
+        const unsigned long long needy = __ballot(emp && !out);
+        if (needy) {
+            const int nn = __popcll(needy);
+            const int rank = __popcll(needy & lt);
+            int t0 = 0, give = 0;
+            bool exhausted = false;
+            if (PAIR) {
+                // pair tasks: claim whole chunks from the root's global counter
+                // only when the wavefront-local range is empty, then hand them out
+                if (tq == tq_end && !pq_done) {
+                    int b = 0;
+                    if (lane == 0) b = atomicAdd(&tctr[slot], kPairChunk);
+                    b = __shfl(b, 0);
+                    if (b < total) {
+                        tq = b;
+                        tq_end = b + kPairChunk < total ? b + kPairChunk : total;
+                    } else {
+                        pq_done = true;
+                    }
+                }
+                t0 = tq;
+                give = min(nn, tq_end - tq);
+                tq += give;
+                exhausted = pq_done && tq == tq_end;
+            } else {
+                t0 = next_task;
+                give = min(nn, total - next_task > 0 ? total - next_task : 0);
+                next_task += give;
+                exhausted = next_task >= total;
+            }
+            if (emp && !out) {
+                if (rank < give) {
+                    const int t = t0 + rank;
+                    sbase = depth = 0;
+                    if (PAIR) {
+                        // pair task t -> (i, j): row i by binary search of pre[],
+                        // j the (t - pre[i])-th set bit of B[i]
+                        int lo = 0, hi = s;                     // pre[lo] <= t < pre[hi]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (pre[mid] <= t) lo = mid; else hi = mid;
+                        }
+                        const int i = lo;
+                        int r = t - pre[i], j = 0;
+                        bool got = false;
+#pragma unroll
+                        for (int w = 0; w < MW; w++) {
+                            const unsigned int x = B[i * STRIDE + w];
+                            const int c = __popc(x);
+                            if (!got && r < c) { j = 32 * w + select_bit(x, r); got = true; }
+                            if (!got) r -= c;
+                        }
+                        unsigned int c2 = 0;
+#pragma unroll
+                        for (int w = 0; w < MW; w++) {
+                            R[w] = B[i * STRIDE + w] & B[j * STRIDE + w];
+                            c2 += __popc(R[w]);
+                        }
+                        p = p0 + 1;
+                        if (STATS) { nodes += 1; wsum += W; }
+                        if (p + 1 == k || p + 2 == k) {
+                            if (p + 1 == k) {
+                                acc += c2;
+                            } else {
+                                acc += leaf_edges<MW, STRIDE>(R, B);
+                                if (STATS) { nodes += c2; wsum += W * c2; }
+                            }
+#pragma unroll
+                            for (int w = 0; w < MW; w++) R[w] = 0u;
+                        }
+                    } else {
+                        unsigned int c2 = 0;
+#pragma unroll
+                        for (int w = 0; w < MW; w++) {
+                            R[w] = B[t * STRIDE + w];
+                            c2 += __popc(R[w]);
+                        }
+                        p = p0;
+                        if (p + 1 == k || p + 2 == k) {
+                            if (p + 1 == k) {
+                                acc += c2;
+                            } else {
+                                acc += leaf_edges<MW, STRIDE>(R, B);
+                                if (STATS) { nodes += c2; wsum += W * c2; }
+                            }
+#pragma unroll
+                            for (int w = 0; w < MW; w++) R[w] = 0u;
+                        }
+                    }
+                } else if (exhausted) {
+                    out = true;
+                }
+            }
+        }
+        // donation: the r-th idle lane takes the shallowest saved level of the
+        // r-th lane that has one
+        bool idle = true;
+#pragma unroll
+        for (int t = 0; t < MW; t++) idle &= R[t] == 0u;
+        idle = idle && depth <= sbase && out;
+        const unsigned long long idle_m = __ballot(idle);
+        const unsigned long long donor_m = __ballot(depth > sbase);
+        if (idle_m != 0ull && donor_m != 0ull) {
+            const int n = min(__popcll(idle_m), __popcll(donor_m));
+            if (depth > sbase) {
+                const int rd = __popcll(donor_m & lt);
+                if (rd < n) {
+                    const unsigned int* f = stk + sbase * SLOT * 64 + lane;
+#pragma unroll
+                    for (int t = 0; t <= MW; t++) mbox[rd * SLOT + t] = f[t * 64];
+                    sbase++;
+                }
+            }
+            wave_sync_lds();
+            if (idle) {
+                const int ri = __popcll(idle_m & lt);
+                if (ri < n) {
+#pragma unroll
+                    for (int t = 0; t < MW; t++) R[t] = mbox[ri * SLOT + t];
+                    p = static_cast<int>(mbox[ri * SLOT + MW]);
+                    depth = sbase = 0;
+                }
+            }
+            wave_sync_lds();
+        }
+        // done with this root when no lane holds work and no task is left
+        bool busy = false;
+#pragma unroll
+        for (int t = 0; t < MW; t++) busy |= R[t] != 0u;
+        busy = busy || depth > sbase;
+        if (__ballot(busy || !out) == 0ull) break;
+        if (busy) {
+            bool has = false;
+#pragma unroll
+            for (int t = 0; t < MW; t++) has |= R[t] != 0u;
+            if (has) {
+                // expand the lowest candidate v
+                int v = 0;
+                bool got = false;
+#pragma unroll
+                for (int t = 0; t < MW; t++) {
+                    if (!got && R[t] != 0u) {
+                        v = 32 * t + __ffs(R[t]) - 1;
+                        R[t] &= R[t] - 1u;
+                        got = true;
+                    }
+                }
+                unsigned int Y[MW];
+                unsigned int c = 0;
+                bool yany = false;
+#pragma unroll
+                for (int t = 0; t < MW; t++) {
+                    Y[t] = R[t] ? (R[t] & B[v * STRIDE + t]) : 0u;
+                    c += __popc(Y[t]);
+                    yany |= Y[t] != 0u;
+                }
+                if (STATS) { nodes += 1; wsum += W; }
+                if (p + 2 == k) {
+                    acc += c;
+                } else if (p + 3 == k) {
+                    // Y holds the (k-1)-th vertex candidates: count the last
+                    // level under it at once instead of descending
+                    if (yany) acc += leaf_edges<MW, STRIDE>(Y, B);
+                    if (STATS) { nodes += c; wsum += W * c; }
+                } else if (yany) {
+                    bool rany = false;
+#pragma unroll
+                    for (int t = 0; t < MW; t++) rany |= R[t] != 0u;
+                    if (rany) {
+                        unsigned int* f = stk + depth * SLOT * 64 + lane;
+#pragma unroll
+                        for (int t = 0; t < MW; t++) f[t * 64] = R[t];
+                        f[MW * 64] = static_cast<unsigned int>(p);
+                        depth++;
+                    }
+#pragma unroll
+                    for (int t = 0; t < MW; t++) R[t] = Y[t];
+                    p++;
+                }
+            }
+        }
+    }
+}
+
 // MAXW: bitset words per row of this root list; EC: edge roots; PAIR: pair
 // tasks + helping (deep trees on wide roots); STATS: count expanded nodes.
 template <int MAXW, bool EC, bool PAIR, bool STATS>
@@ -99,17 +378,24 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
     const int nwaves = gridDim.x;                   // one wavefront per block
     const unsigned long long lt = lanemask_lt();
 
-    unsigned long long acc = 0, nodes = 0, wsum = 0;
+    unsigned long long acc = 0, nodes = 0, wsum = 0, iters = 0;
+    const unsigned long long t_begin = STATS ? __builtin_amdgcn_s_memrealtime() : 0ull;
     bool helping = false;
+    int rq = 0, rq_end = 0;                         // claimed, unprocessed root range
+    constexpr int RC = PAIR ? 1 : kRootChunk;
 
     for (;;) {
         // ---------------------------------------------------------- root
         int slot = -1;
         if (!helping) {
-            int r = 0;
-            if (lane == 0) r = atomicAdd(P.head, 1);
-            r = __shfl(r, 0);
-            if (r < nroots) slot = r;
+            if (rq == rq_end) {
+                int r = 0;
+                if (lane == 0) r = atomicAdd(P.head, RC);
+                r = __shfl(r, 0);
+                rq = r < nroots ? r : nroots;
+                rq_end = r + RC < nroots ? r + RC : nroots;
+            }
+            if (rq < rq_end) slot = rq++;
             else if (PAIR) helping = true;
             else break;
         }
@@ -145,210 +431,27 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
             wave_sync_lds();
             continue;
         }
-        extract_rows<1, false>(s, P.row_ptr, P.col, lane, S, B, STRIDE);
-        const unsigned long long W = static_cast<unsigned long long>((s + 31) >> 5);
-
-        int total = s;                                   // tasks of this root
-        if (PAIR) {
-            // pre[i] = number of pair tasks before row i
-            int run = 0;
-            for (int b0 = 0; b0 < s; b0 += 64) {
-                const int i = b0 + lane;
-                int c = 0;
-                if (i < s) {
-#pragma unroll
-                    for (int t = 0; t < MAXW; t++) c += __popc(B[i * STRIDE + t]);
-                }
-                int inc = c;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int y = __shfl_up(inc, off, 64);
-                    if (lane >= off) inc += y;
-                }
-                if (i < s) pre[i] = run + inc - c;
-                run += __shfl(inc, 63);
-            }
-            if (lane == 0) pre[s] = run;
-            wave_sync_lds();
-            total = run;
-            if (!helping && lane == 0) {
-                __hip_atomic_store(&ttot[slot], run + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&P.active[blockIdx.x], slot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
+        // rows padded only to the smallest supported width holding this root
+        const int Wr = __builtin_amdgcn_readfirstlane((s + 31) >> 5);
+        if constexpr (MAXW >= 32) {
+            if (Wr > 16) { walk_root<32, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
         }
-
-        // ---------------------------------------------------- traversal
-        unsigned int R[MAXW];
-#pragma unroll
-        for (int t = 0; t < MAXW; t++) R[t] = 0u;
-        int p = 0, depth = 0, sbase = 0;
-        bool out = false;                                // no task left for this lane
-        int next_task = 0;                               // vertex tasks: wave counter
-
-        for (;;) {
-            bool emp = true;
-#pragma unroll
-            for (int t = 0; t < MAXW; t++) emp &= R[t] == 0u;
-            // pop a saved level
-            if (emp && depth > sbase) {
-                depth--;
-                const unsigned int* f = stk + depth * SLOT * 64 + lane;
-#pragma unroll
-                for (int t = 0; t < MAXW; t++) R[t] = f[t * 64];
-                p = static_cast<int>(f[MAXW * 64]);
-                emp = false;
-            }
-            // claim tasks for lanes that have nothing
-            const unsigned long long needy = __ballot(emp && !out);
-            if (needy) {
-                const int nn = __popcll(needy);
-                const int rank = __popcll(needy & lt);
-                int t0;
-                if (PAIR) {
-                    int b = 0;
-                    if (lane == 0) b = atomicAdd(&tctr[slot], nn);
-                    t0 = __shfl(b, 0);
-                } else {
-                    t0 = next_task;
-                    next_task += nn;
-                }
-                if (emp && !out) {
-                    const int t = t0 + rank;
-                    if (t < total) {
-                        sbase = depth = 0;
-                        if (PAIR) {
-                            // pair task t -> (i, j): row i by binary search of pre[],
-                            // j the (t - pre[i])-th set bit of B[i]
-                            int lo = 0, hi = s;                     // pre[lo] <= t < pre[hi]
-                            while (hi - lo > 1) {
-                                const int mid = (lo + hi) >> 1;
-                                if (pre[mid] <= t) lo = mid; else hi = mid;
-                            }
-                            const int i = lo;
-                            int r = t - pre[i], j = 0;
-                            bool got = false;
-#pragma unroll
-                            for (int w = 0; w < MAXW; w++) {
-                                const unsigned int x = B[i * STRIDE + w];
-                                const int c = __popc(x);
-                                if (!got && r < c) { j = 32 * w + select_bit(x, r); got = true; }
-                                if (!got) r -= c;
-                            }
-                            unsigned int c2 = 0;
-#pragma unroll
-                            for (int w = 0; w < MAXW; w++) {
-                                R[w] = B[i * STRIDE + w] & B[j * STRIDE + w];
-                                c2 += __popc(R[w]);
-                            }
-                            p = p0 + 1;
-                            if (STATS) { nodes += 1; wsum += W; }
-                            if (p + 1 == k) {
-                                acc += c2;
-#pragma unroll
-                                for (int w = 0; w < MAXW; w++) R[w] = 0u;
-                            }
-                        } else {
-                            unsigned int c2 = 0;
-#pragma unroll
-                            for (int w = 0; w < MAXW; w++) {
-                                R[w] = B[t * STRIDE + w];
-                                c2 += __popc(R[w]);
-                            }
-                            p = p0;
-                            if (p + 1 == k) {
-                                acc += c2;
-#pragma unroll
-                                for (int w = 0; w < MAXW; w++) R[w] = 0u;
-                            }
-                        }
-                    } else {
-                        out = true;
-                    }
-                }
-            }
-            // donation: the r-th idle lane takes the shallowest saved level of the
-            // r-th lane that has one
-            bool idle = true;
-#pragma unroll
-            for (int t = 0; t < MAXW; t++) idle &= R[t] == 0u;
-            idle = idle && depth <= sbase && out;
-            const unsigned long long idle_m = __ballot(idle);
-            const unsigned long long donor_m = __ballot(depth > sbase);
-            if (idle_m != 0ull && donor_m != 0ull) {
-                const int n = min(__popcll(idle_m), __popcll(donor_m));
-                if (depth > sbase) {
-                    const int rd = __popcll(donor_m & lt);
-                    if (rd < n) {
-                        const unsigned int* f = stk + sbase * SLOT * 64 + lane;
-#pragma unroll
-                        for (int t = 0; t <= MAXW; t++) mbox[rd * SLOT + t] = f[t * 64];
-                        sbase++;
-                    }
-                }
-                wave_sync_lds();
-                if (idle) {
-                    const int ri = __popcll(idle_m & lt);
-                    if (ri < n) {
-#pragma unroll
-                        for (int t = 0; t < MAXW; t++) R[t] = mbox[ri * SLOT + t];
-                        p = static_cast<int>(mbox[ri * SLOT + MAXW]);
-                        depth = sbase = 0;
-                    }
-                }
-                wave_sync_lds();
-            }
-            // done with this root when no lane holds work and no task is left
-            bool busy = false;
-#pragma unroll
-            for (int t = 0; t < MAXW; t++) busy |= R[t] != 0u;
-            busy = busy || depth > sbase;
-            if (__ballot(busy || !out) == 0ull) break;
-            if (busy) {
-                bool has = false;
-#pragma unroll
-                for (int t = 0; t < MAXW; t++) has |= R[t] != 0u;
-                if (has) {
-                    // expand the lowest candidate v
-                    int v = 0;
-                    bool got = false;
-#pragma unroll
-                    for (int t = 0; t < MAXW; t++) {
-                        if (!got && R[t] != 0u) {
-                            v = 32 * t + __ffs(R[t]) - 1;
-                            R[t] &= R[t] - 1u;
-                            got = true;
-                        }
-                    }
-                    unsigned int Y[MAXW];
-                    unsigned int c = 0;
-                    bool yany = false;
-#pragma unroll
-                    for (int t = 0; t < MAXW; t++) {
-                        Y[t] = R[t] ? (R[t] & B[v * STRIDE + t]) : 0u;
-                        c += __popc(Y[t]);
-                        yany |= Y[t] != 0u;
-                    }
-                    if (STATS) { nodes += 1; wsum += W; }
-                    if (p + 2 == k) {
-                        acc += c;
-                    } else if (yany) {
-                        bool rany = false;
-#pragma unroll
-                        for (int t = 0; t < MAXW; t++) rany |= R[t] != 0u;
-                        if (rany) {
-                            unsigned int* f = stk + depth * SLOT * 64 + lane;
-#pragma unroll
-                            for (int t = 0; t < MAXW; t++) f[t * 64] = R[t];
-                            f[MAXW * 64] = static_cast<unsigned int>(p);
-                            depth++;
-                        }
-#pragma unroll
-                        for (int t = 0; t < MAXW; t++) R[t] = Y[t];
-                        p++;
-                    }
-                }
-            }
+        if constexpr (MAXW >= 16) {
+            if (Wr > 8) { walk_root<16, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
         }
+        if constexpr (MAXW >= 8) {
+            if (Wr > 6) { walk_root<8, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
+            if (Wr > 4) { walk_root<6, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
+        }
+        if constexpr (MAXW >= 4) {
+            if (Wr > 3) { walk_root<4, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
+            if (Wr > 2) { walk_root<3, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
+        }
+        if constexpr (MAXW >= 2) {
+            if (Wr > 1) { walk_root<2, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
+        }
+        walk_root<1, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters);
+    root_done:
         if (PAIR && !helping && lane == 0)
             __hip_atomic_store(&P.active[blockIdx.x], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (P.gacc) flush_root(P, graph, acc);
@@ -364,12 +467,19 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
         if (lane == 0) {
             atomicAdd(P.stats, nodes);
             atomicAdd(P.stats + 1, wsum);
+            atomicAdd(P.iters, iters);
+            // busy time of this wavefront and the span of the whole grid
+            // (100 MHz constant clock): [sum of busy, min start, max end]
+            const unsigned long long t_end = __builtin_amdgcn_s_memrealtime();
+            atomicAdd(P.timing, t_end - t_begin);
+            atomicMin(P.timing + 1, t_begin);
+            atomicMax(P.timing + 2, t_end);
         }
     }
 }
 
 template <int MAXW, bool EC, bool PAIR>
-int launch_lane_t(const LaneParams& base, bool stats, hipStream_t s) {
+int launch_lane_t(const LaneParams& base, bool stats, int* grid_out, hipStream_t s) {
     constexpr int SLOT = MAXW + 1;
     LaneParams P = base;
     P.s_cap = 32 * MAXW;
@@ -386,15 +496,16 @@ int launch_lane_t(const LaneParams& base, bool stats, hipStream_t s) {
     KC_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64, lds_bytes));
     if (occ < 1) return KC_EUNSUPPORTED;
     if (occ > kLaneWavesPerCU) occ = kLaneWavesPerCU;   // the registry holds one entry per wavefront
+    if (grid_out) *grid_out = device_cus() * occ;
     kern<<<device_cus() * occ, 64, lds_bytes, s>>>(P);
     KC_CHECK(hipGetLastError());
     return KC_OK;
 }
 
 template <int MAXW>
-int launch_lane_m(const LaneParams& P, bool ec, bool pair, bool stats, hipStream_t s) {
-    if (ec) return pair ? launch_lane_t<MAXW, true, true>(P, stats, s) : launch_lane_t<MAXW, true, false>(P, stats, s);
-    return pair ? launch_lane_t<MAXW, false, true>(P, stats, s) : launch_lane_t<MAXW, false, false>(P, stats, s);
+int launch_lane_m(const LaneParams& P, bool ec, bool pair, bool stats, int* g, hipStream_t s) {
+    if (ec) return pair ? launch_lane_t<MAXW, true, true>(P, stats, g, s) : launch_lane_t<MAXW, true, false>(P, stats, g, s);
+    return pair ? launch_lane_t<MAXW, false, true>(P, stats, g, s) : launch_lane_t<MAXW, false, false>(P, stats, g, s);
 }
 
 }  // namespace
@@ -414,6 +525,8 @@ int lane_launch(const LaneLaunch& L, hipStream_t s) {
     P.active = L.active;
     P.acc = L.acc;
     P.stats = L.stats_ptr;
+    P.iters = L.iters_ptr;
+    P.timing = L.timing_ptr;
     P.gacc = L.gacc;
     P.gid = L.gid;
     const int p0 = L.ec ? 3 : 2;
@@ -423,12 +536,12 @@ int lane_launch(const LaneLaunch& L, hipStream_t s) {
     P.levels = k_levels(L.k, first);
     P.s_cap = 0;
     switch (L.maxw) {
-        case 1: return launch_lane_m<1>(P, L.ec, L.pair, L.stats, s);
-        case 2: return launch_lane_m<2>(P, L.ec, L.pair, L.stats, s);
-        case 4: return launch_lane_m<4>(P, L.ec, L.pair, L.stats, s);
-        case 8: return launch_lane_m<8>(P, L.ec, L.pair, L.stats, s);
-        case 16: return launch_lane_m<16>(P, L.ec, L.pair, L.stats, s);
-        case 32: return launch_lane_m<32>(P, L.ec, L.pair, L.stats, s);
+        case 1: return launch_lane_m<1>(P, L.ec, L.pair, L.stats, L.grid_out, s);
+        case 2: return launch_lane_m<2>(P, L.ec, L.pair, L.stats, L.grid_out, s);
+        case 4: return launch_lane_m<4>(P, L.ec, L.pair, L.stats, L.grid_out, s);
+        case 8: return launch_lane_m<8>(P, L.ec, L.pair, L.stats, L.grid_out, s);
+        case 16: return launch_lane_m<16>(P, L.ec, L.pair, L.stats, L.grid_out, s);
+        case 32: return launch_lane_m<32>(P, L.ec, L.pair, L.stats, L.grid_out, s);
         default: return KC_EINVAL;
     }
 }

@@ -112,7 +112,7 @@ struct kc_server {
     }
 
     void worker(int idx) {
-        hipSetDevice(device);
+        (void)hipSetDevice(device);
         hipStream_t s = streams[idx];
         for (;;) {
             kc::Query* q = nullptr;
@@ -158,8 +158,8 @@ extern "C" KC_API int32_t kc_server_create(const kc_dag* dags, int32_t ndags, in
     sv->streams.resize(slots);
     for (int i = 0; i < slots; i++) {
         if (hipStreamCreateWithFlags(&sv->streams[i], hipStreamNonBlocking) != hipSuccess) {
-            for (int j = 0; j < i; j++) hipStreamDestroy(sv->streams[j]);
-            hipFree(sv->arena_mem);
+            for (int j = 0; j < i; j++) (void)hipStreamDestroy(sv->streams[j]);
+            (void)hipFree(sv->arena_mem);
             delete sv->arena;
             delete sv;
             return KC_EDEVICE;
@@ -233,8 +233,8 @@ extern "C" KC_API int32_t kc_server_destroy(kc_server* sv) {
     sv->cv_work.notify_all();
     for (auto& t : sv->workers) t.join();
     for (auto& kv : sv->all) delete kv.second;
-    for (auto s : sv->streams) hipStreamDestroy(s);
-    hipFree(sv->arena_mem);
+    for (auto s : sv->streams) (void)hipStreamDestroy(s);
+    (void)hipFree(sv->arena_mem);
     delete sv->arena;
     delete sv;
     return KC_OK;
