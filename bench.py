@@ -110,9 +110,11 @@ def bench_batched(kc, ngraphs, k, reps):
     plain = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for g in graphs:
+    for i, g in enumerate(graphs):
         d = kc.orient(g, kc.ORDER_DEGREE, validate=False, ws=ows, out=dag)
         plain.append(kc.count(d, k, ws=cws))
+        if (i + 1) % 2000 == 0:
+            log("plain: %d graphs (%.1f s)" % (i + 1, time.perf_counter() - t0))
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     mism = sum(1 for x, y in zip(batched, plain) if x != y)
@@ -185,6 +187,7 @@ def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, see
         t0 = time.perf_counter()
         res = kc.replay_trace(sv, [(0.0, g, k, p) for g, k, p in qs[:nwarm]])
         seq_rate = nwarm / (time.perf_counter() - t0)
+    log("served: sequential service rate %.1f queries/s" % seq_rate)
     lam = util * seq_rate
     gaps = rng.exponential(1.0 / lam, size=nq)
     arr = np.cumsum(gaps) - gaps[0]
@@ -196,6 +199,7 @@ def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, see
             rs = kc.replay_trace(sv, trace)
             span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
         lat = [r.latency * 1e3 for r in rs]
+        log("served: %s pass done (%.1f s)" % (name, span))
         out[name] = {"slots": nslots, "queries_per_s": len(rs) / span, "p50_ms": round(percentile(lat, 50), 3),
                      "p99_ms": round(percentile(lat, 99), 3), "mean_ms": round(sum(lat) / len(lat), 3),
                      "refused": sum(1 for r in rs if r.status == kc.ENOMEM),
@@ -207,6 +211,7 @@ def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, see
         with kc.Server(dags, slots=nslots, mem_budget=budget) as sv:
             rs = kc.replay_trace(sv, [(0.0, g, k, p) for _, g, k, p in trace])
             span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
+        log("served: %s pass done (%.1f s)" % (name, span))
         out[name] = {"queries_per_s": len(rs) / span}
     out.update({
         "workload": "%d graphs (n log-uniform [%d, %d], shapes power-law / dense-core / batch-like), %d queries "
@@ -230,6 +235,7 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=0)
     ap.add_argument("--scheme", type=int, default=2)
+    ap.add_argument("--no-handoff", action="store_true", help="keep subtrees on the wavefront that found them")
     ap.add_argument("--cpu-frac", type=float, default=0.005)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=10000)
@@ -245,10 +251,12 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-util", type=float, default=0.7)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not an implemented path)", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the counting path runs on a single MI355X; "
+              "sharding over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -264,6 +272,17 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe_mib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings give
+        # the scale of the counters for the kernels that follow
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x %d bytes" % nb)
+        del src, dst
     csr = kc.to_device(g, dev)
     m = g.m
     order = kc.ORDER_DEGENERACY
@@ -282,7 +301,8 @@ def main():
         out = {}
         for k in ks:
             p = kc.Profile()
-            out[k] = kc.count(dag, k, scheme=args.scheme, width=args.width, ws=cws, profile=p)
+            out[k] = kc.count(dag, k, scheme=args.scheme, width=args.width, ws=cws, profile=p,
+                              handoff=not args.no_handoff)
             profiles.setdefault(k, []).append(p)
         return out
 
@@ -313,7 +333,8 @@ def main():
                          "classify_ms": round(sum(p.ms_classify for p in ps) / len(ps), 3),
                          "light_ms": round(ml, 3), "heavy_ms": round(mh, 3),
                          "width_list_ms": [round(x, 3) for x in mw],
-                         "width_list_roots": [int(ps[0].roots_width[j]) for j in range(6)]}
+                         "width_list_roots": [int(ps[0].roots_width[j]) for j in range(6)],
+                         "width_list_handoffs": [int(ps[-1].items_width[j]) for j in range(6)]}
         for j in range(6):
             phases.append((mw[j], k, j))
 
@@ -321,7 +342,8 @@ def main():
     # from a separate, untimed stats pass of the same call
     dom_ms, dom_k, dom_j = max(phases)
     sp = kc.Profile()
-    c_stats = kc.count(dag, dom_k, scheme=args.scheme, width=args.width, ws=cws, profile=sp, collect_stats=True)
+    c_stats = kc.count(dag, dom_k, scheme=args.scheme, width=args.width, ws=cws, profile=sp, collect_stats=True,
+                       handoff=not args.no_handoff)
     assert c_stats == counts[dom_k]
     work_ops = 2.0 * sp.words_width[dom_j]
     achieved = work_ops / (dom_ms / 1e3) / 1e12
@@ -335,11 +357,14 @@ def main():
         "frac": round(achieved / VALU_PEAK_TOPS, 5),
         "traffic": None,
         "work": "2 int32 ops (AND + popcount) per bitset word per expanded tree node: "
-                "%d nodes x %d-word rows = %d words in one launch of %.3f ms (HIP events, mean of timed steps)"
+                "%d nodes with rows of at most %d words (the root's own word count each) = %d words in one "
+                "launch of %.3f ms (HIP events, mean of timed steps)"
                 % (sp.nodes_width[dom_j], 1 << dom_j, sp.words_width[dom_j], dom_ms),
-        "lane_utilisation": round(sp.nodes_width[dom_j] / max(1, 64 * sp.iters_width[dom_j]), 4),
+        "lane_utilisation": round(sp.expand_width[dom_j] / max(1, 64 * sp.iters_width[dom_j]), 4),
         "wavefront_busy_fraction": round(float(sp.busy_width[dom_j]), 4),
         "wavefronts": int(sp.waves_width[dom_j]),
+        "width_list_busy_fraction": [round(float(sp.busy_width[j]), 4) for j in range(6)],
+        "width_list_nodes": [int(sp.nodes_width[j]) for j in range(6)],
     }
 
     batched = None

@@ -109,10 +109,12 @@ typedef struct kc_profile {
     int32_t roots_width[6];
     uint64_t nodes_width[6];
     uint64_t words_width[6];
-    uint64_t iters_width[6];   /* wavefront loop iterations (lane utilisation =
-                                  nodes / (64 x iterations))                    */
+    uint64_t iters_width[6];   /* wavefront loop iterations                      */
+    uint64_t expand_width[6];  /* lane-iterations that expanded a node (lane
+                                  utilisation = expand / (64 x iterations))     */
     int32_t waves_width[6];    /* wavefronts launched                           */
     float busy_width[6];       /* mean wavefront busy time / launch span         */
+    int32_t items_width[6];    /* subtrees handed between wavefronts (pair mode) */
 } kc_profile;
 
 /* Tuning options; NULL means defaults.  scheme: KC_SCHEME_*; width: lanes per
@@ -124,7 +126,8 @@ typedef struct kc_opts {
     int32_t scheme;
     int32_t width;
     int32_t collect_stats;
-    int32_t reserved;
+    int32_t no_handoff;        /* 1: wavefronts never hand subtrees to idle ones
+                                  (deep non-pivot counts; for measurement)     */
     uint64_t test_preload;
     kc_profile* profile;
 } kc_opts;

@@ -58,13 +58,14 @@ class Profile(ctypes.Structure):
                 ("light_roots", ctypes.c_int32), ("heavy_roots", ctypes.c_int32),
                 ("ms_width", ctypes.c_float * 6), ("roots_width", ctypes.c_int32 * 6),
                 ("nodes_width", ctypes.c_uint64 * 6), ("words_width", ctypes.c_uint64 * 6),
-                ("iters_width", ctypes.c_uint64 * 6), ("waves_width", ctypes.c_int32 * 6),
-                ("busy_width", ctypes.c_float * 6)]
+                ("iters_width", ctypes.c_uint64 * 6), ("expand_width", ctypes.c_uint64 * 6),
+                ("waves_width", ctypes.c_int32 * 6),
+                ("busy_width", ctypes.c_float * 6), ("items_width", ctypes.c_int32 * 6)]
 
 
 class _Opts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("width", ctypes.c_int32),
-                ("collect_stats", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("collect_stats", ctypes.c_int32), ("no_handoff", ctypes.c_int32),
                 ("test_preload", ctypes.c_uint64), ("profile", ctypes.POINTER(Profile))]
 
 
@@ -188,8 +189,8 @@ def orient(g: Csr, order: int = ORDER_DEGREE, validate: bool = True, ws: torch.T
 
 
 def _opts(scheme: int, width: int, test_preload: int, profile: Profile | None = None,
-          collect_stats: bool = False) -> _Opts:
-    o = _Opts(scheme, width, int(bool(collect_stats)), 0, test_preload, None)
+          collect_stats: bool = False, handoff: bool = True) -> _Opts:
+    o = _Opts(scheme, width, int(bool(collect_stats)), int(not handoff), test_preload, None)
     if profile is not None:
         o.profile = ctypes.pointer(profile)
     return o
@@ -203,11 +204,11 @@ def count_workspace_bytes(d: Dag, k: int, pivot: bool, scheme: int = 0, width: i
 
 def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
                  ws: torch.Tensor | None = None, test_preload: int = 0, stream=None,
-                 profile: Profile | None = None, collect_stats: bool = False):
+                 profile: Profile | None = None, collect_stats: bool = False, handoff: bool = True):
     """(status, count) of kc_count without raising."""
     L = lib()
     cd = d._c()
-    o = _opts(scheme, width, test_preload, profile, collect_stats)
+    o = _opts(scheme, width, test_preload, profile, collect_stats, handoff)
     need = int(L.kc_count_workspace(ctypes.byref(cd), k, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)
@@ -219,9 +220,10 @@ def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
 
 def count(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
           ws: torch.Tensor | None = None, stream=None, profile: Profile | None = None,
-          collect_stats: bool = False) -> int:
-    """Number of k-cliques (kc_count); exact Python int."""
-    st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream, profile, collect_stats)
+          collect_stats: bool = False, handoff: bool = True) -> int:
+    """Number of k-cliques (kc_count); exact Python int.  handoff=False keeps
+    every subtree on the wavefront that found it (measurement)."""
+    st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream, profile, collect_stats, handoff)
     if st != OK:
         raise KcError(st, "kc_count")
     return val

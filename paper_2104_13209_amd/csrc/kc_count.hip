@@ -106,29 +106,44 @@ __global__ void __launch_bounds__(kBlock) k_classify(int nroots_total, int need,
     }
 }
 
-// Width lists: root r goes to list w when its bound on |S| needs 2^w words per
-// bitset row (1, 2, 4, 8, 16 or 32); pass 1 counts, pass 2 appends into
-// consecutive segments of one array (the order inside a list is unspecified).
+// Width lists: root r goes to list w when its |S| needs 2^w words per bitset
+// row (1, 2, 4, 8, 16 or 32); pass 1 counts, pass 2 appends into consecutive
+// segments of one array (the order inside a list is unspecified).
 __device__ __forceinline__ int width_list(int bound) {
     return bound <= 32 ? 0 : bound <= 64 ? 1 : bound <= 128 ? 2 : bound <= 256 ? 3 : bound <= 512 ? 4 : 5;
 }
 
+// |S| of root r: |N+(u)| for a vertex root; for the edge root (u, v) the size
+// of N+(u) ∩ N+(v), counted exactly (rows are ascending, and every common
+// vertex lies after v in the row of u).  Sizes below `need` are only bounded.
 template <bool EC>
-__device__ __forceinline__ int root_bound(int r, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                                          const int* __restrict__ src) {
-    if (EC) {
-        const int u = src[r], v = col[r];
-        const int du = row_ptr[u + 1] - row_ptr[u] - 1;
-        const int dv = row_ptr[v + 1] - row_ptr[v];
-        return du < dv ? du : dv;
+__device__ __forceinline__ int root_size(int r, int need, const int* __restrict__ row_ptr,
+                                         const int* __restrict__ col, const int* __restrict__ src) {
+    if (!EC) return row_ptr[r + 1] - row_ptr[r];
+    const int u = src[r], v = col[r];
+    const int a0 = r + 1, na = row_ptr[u + 1] - a0;
+    const int b0 = row_ptr[v], nb = row_ptr[v + 1] - b0;
+    if (na < need || nb < need) return na < nb ? na : nb;
+    const int* x = col + (na <= nb ? a0 : b0);          // shorter row: probes
+    const int* y = col + (na <= nb ? b0 : a0);          // longer row: searched
+    const int nx = na <= nb ? na : nb, ny = na <= nb ? nb : na;
+    int c = 0, lo = 0;
+    for (int i = 0; i < nx && lo < ny; i++) {
+        const int t = x[i];
+        int hi = ny;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (y[mid] < t) lo = mid + 1; else hi = mid;
+        }
+        if (lo < ny && y[lo] == t) c++;
     }
-    return row_ptr[r + 1] - row_ptr[r];
+    return c;
 }
 
 template <bool EC, bool FILL>
 __global__ void __launch_bounds__(kBlock) k_classify_w(int nroots_total, int need, const int* __restrict__ row_ptr,
                                                       const int* __restrict__ col, const int* __restrict__ src,
-                                                      int* lists, int* ctl) {
+                                                      int* lists, int* ctl, int* lst_of) {
     const int lane = threadIdx.x & 63;
     int off[kWidthLists];
     if (FILL) {
@@ -142,8 +157,13 @@ __global__ void __launch_bounds__(kBlock) k_classify_w(int nroots_total, int nee
         const int r = base + threadIdx.x;
         int lst = -1;
         if (r < nroots_total) {
-            const int bound = root_bound<EC>(r, row_ptr, col, src);
-            if (bound >= need && bound >= 0) lst = width_list(bound);
+            if (FILL) {
+                lst = lst_of[r];                    // from the counting pass
+            } else {
+                const int size = root_size<EC>(r, need, row_ptr, col, src);
+                if (size >= need && size >= 0) lst = width_list(size);
+                lst_of[r] = lst;
+            }
         }
         for (int j = 0; j < kWidthLists; j++) {
             const unsigned long long m = __ballot(lst == j);
@@ -469,11 +489,13 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         if (k >= (ec ? 3 : 2) + 4) {
             KC_CHECK(hipMemsetAsync(w.task_ctr, 0, sizeof(int) * static_cast<size_t>(nroots), s));
             KC_CHECK(hipMemsetAsync(w.task_tot, 0, sizeof(int) * static_cast<size_t>(nroots), s));
+            KC_CHECK(hipMemsetAsync(w.qctl, 0, sizeof(int) * kQueueCtlWords * kWidthLists, s));
+            KC_CHECK(hipMemsetAsync(w.qready, 0, sizeof(int) * kQueueCap * kWidthLists, s));
         }
         if (ec)
-            k_classify_w<true, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+            k_classify_w<true, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl, w.heavy);
         else
-            k_classify_w<false, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+            k_classify_w<false, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl, w.heavy);
     } else if (ec) {
         k_classify<true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
     } else {
@@ -488,9 +510,9 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         // lane walks over the width lists, widest first so that the largest roots
         // start early; profile: heavy = lists with >= 4 words, light = 1-2 words
         if (ec)
-            k_classify_w<true, true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+            k_classify_w<true, true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl, w.heavy);
         else
-            k_classify_w<false, true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl);
+            k_classify_w<false, true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl, w.heavy);
         KC_CHECK(hipGetLastError());
         if (prof) KC_CHECK(hipEventRecord(pe->ev[1], s));
         const int p0 = ec ? 3 : 2;
@@ -517,8 +539,13 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.active = w.active;
             L.acc = w.acc;
             L.stats_ptr = w.acc + 6 + 2 * lst;
-            L.iters_ptr = w.acc + 6 + 2 * kWidthLists + lst;
-            L.timing_ptr = w.acc + 6 + 3 * kWidthLists + 3 * lst;
+            L.iters_ptr = w.acc + 6 + 2 * kWidthLists + 2 * lst;
+            L.timing_ptr = w.acc + 6 + 4 * kWidthLists + 3 * lst;
+            L.steal = L.pair && !(o && o->no_handoff);
+            L.qctl = w.qctl + kQueueCtlWords * lst;
+            L.qready = w.qready + static_cast<size_t>(kQueueCap) * lst;
+            L.qitems = w.qitems;
+            L.flags = w.ctl + CC_FLAGS;
             if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst], s));
             L.grid_out = &lane_grid[lst];
             st = lane_launch(L, s);
@@ -586,6 +613,10 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     }
     KC_CHECK(hipMemcpyAsync(res, w.acc, kAccWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     KC_CHECK(hipMemcpyAsync(hctl, w.ctl, CC_WORDS * sizeof(int), hipMemcpyDeviceToHost, s));
+    int hq[kQueueCtlWords * kWidthLists] = {};
+    const bool queued = lane_path && k >= (ec ? 3 : 2) + 4;
+    if (prof && queued)
+        KC_CHECK(hipMemcpyAsync(hq, w.qctl, sizeof(hq), hipMemcpyDeviceToHost, s));
     if (counts_out)
         KC_CHECK(hipMemcpyAsync(counts_out, w.counts, 2 * sizeof(unsigned long long) * counts_len,
                                 hipMemcpyDeviceToHost, s));
@@ -610,9 +641,11 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             prof->waves_width[j] = lane_path ? lane_grid[j] : 0;
             prof->nodes_width[j] = lane_path && stats ? res[6 + 2 * j] : 0;
             prof->words_width[j] = lane_path && stats ? res[7 + 2 * j] : 0;
-            prof->iters_width[j] = lane_path && stats ? res[6 + 2 * kWidthLists + j] : 0;
+            prof->iters_width[j] = lane_path && stats ? res[6 + 2 * kWidthLists + 2 * j] : 0;
+            prof->items_width[j] = queued ? hq[kQueueCtlWords * j + 1] : 0;   // queue tail
+            prof->expand_width[j] = lane_path && stats ? res[7 + 2 * kWidthLists + 2 * j] : 0;
             {
-                const unsigned long long* tm = res + 6 + 3 * kWidthLists + 3 * j;
+                const unsigned long long* tm = res + 6 + 4 * kWidthLists + 3 * j;
                 const double span = tm[2] > tm[1] && tm[1] != ~0ull ? static_cast<double>(tm[2] - tm[1]) : 0.0;
                 prof->busy_width[j] = lane_path && stats && span > 0 && prof->waves_width[j] > 0
                                           ? static_cast<float>(static_cast<double>(tm[0]) / (span * prof->waves_width[j]))
@@ -684,6 +717,7 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     if (st != KC_OK) return st;
     count->lo = res[0];
     count->hi = pivot ? res[1] : 0ull;
+    if (hctl[CC_FLAGS] & 2) return KC_EDEVICE;   // subtree queue stalled: no valid count
     if (pivot && (hctl[CC_FLAGS] & 1)) return KC_EOVERFLOW;
     if (!pivot && res[1] != 0) return KC_EOVERFLOW;
     return KC_OK;

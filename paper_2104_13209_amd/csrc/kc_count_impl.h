@@ -9,7 +9,10 @@ constexpr int kLightCap = 64;          // |S| bound of the light root list
 constexpr int kPivBlocksPerCU = 8;     // grid cap of the heavy pivot kernel (sizes its stacks)
 constexpr int kLaneWavesPerCU = 32;    // grid cap of the lane-walk kernel (sizes its registry)
 constexpr int kWidthLists = 6;         // root lists by bitset words per row: 1, 2, 4, 8, 16, 32
-constexpr int kAccWords = 6 + 6 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, busy, start, end
+constexpr int kQueueCap = 16384;        // lane walk: ring slots for subtrees handed between wavefronts (power of 2)
+constexpr int kItemWords = 36;          // queue item: root slot, path length, 2 spare, 32 words of R
+constexpr int kQueueCtlWords = 8;       // per width list: head, tail, pending, rooting, hungry
+constexpr int kAccWords = 6 + 7 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, expansions, busy, start, end
 
 enum CountCtl {
     CC_LIGHT_N = 0,      // light root count
@@ -60,6 +63,9 @@ struct CountWs {
     int* task_ctr;                // lane walk, pair tasks: claimed tasks per root
     int* task_tot;                // lane walk, pair tasks: total tasks + 1 per root (0 = unpublished)
     int* active;                  // lane walk: root slot owned by each wavefront (-1 = none)
+    int* qctl;                    // lane walk, subtree queue: kQueueCtlWords per width list
+    int* qready;                  // lane walk, subtree queue: slot sequence words, kQueueCap per width list
+    unsigned int* qitems;         // lane walk, subtree queue: kItemWords per item
     int nactive;
     int binom_n;
     size_t slab_words;
@@ -78,6 +84,9 @@ inline CountWs carve_count(void* ws, const kc_dag* d, bool pivot, size_t* bytes)
     w.task_tot = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
     w.nactive = device_cus() * kLaneWavesPerCU;
     w.active = c.take<int>(static_cast<size_t>(w.nactive));
+    w.qctl = c.take<int>(kQueueCtlWords * kWidthLists);
+    w.qready = c.take<int>(static_cast<size_t>(kQueueCap) * kWidthLists);
+    w.qitems = c.take<unsigned int>(static_cast<size_t>(kQueueCap) * kItemWords);
     if (pivot) {
         const int s_cap = s_cap_for(d->d_max);
         w.binom_n = s_cap + 2;
@@ -129,6 +138,11 @@ struct LaneLaunch {
     int* task_ctr;
     int* task_tot;
     int* active;
+    bool steal = false;   // hand subtrees to idle wavefronts through a global queue (pair mode)
+    int* qctl = nullptr;  // this list's queue control words (zero at launch)
+    int* qready = nullptr;  // this list's ring slot sequence words (zero at launch)
+    unsigned int* qitems = nullptr;
+    int* flags = nullptr;   // bit 1 set when the queue stalls (the count is then invalid)
     unsigned long long* acc;
     unsigned long long* stats_ptr;
     unsigned long long* iters_ptr = nullptr;

@@ -29,6 +29,12 @@ namespace {
 
 constexpr int kPairChunk = 64;    // pair tasks claimed per global atomic
 constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
+constexpr int kStealEvery = 128;  // loop iterations between looks at the subtree queue
+constexpr int kStealMax = 8;      // subtrees handed over per look
+// queue control words
+constexpr int Q_HEAD = 0, Q_TAIL = 1, Q_PENDING = 2, Q_ROOTING = 3, Q_HUNGRY = 4;
+constexpr unsigned long long kStallTicks = 2000000000ull;   // 20 s at 100 MHz without queue progress
+constexpr int kReadySpins = 1 << 22;                         // wait for a reserved item's flag
 
 struct LaneParams {
     int k;
@@ -46,10 +52,16 @@ struct LaneParams {
     int* active;                    // pair mode: root slot owned by each wavefront, -1 if none
     unsigned long long* acc;        // [lo, hi]
     unsigned long long* stats;      // [nodes, words]
-    unsigned long long* iters;      // traversal loop iterations (per wavefront, summed)
+    unsigned long long* iters;      // [traversal loop iterations per wavefront, lane expansions], summed
     unsigned long long* timing;     // [sum of wavefront busy ticks, min start, max end]
     unsigned long long* gacc;       // batched: per-graph {lo, hi}; null otherwise
     const int* __restrict__ gid;    // batched: graph of each DAG vertex
+    bool steal;                     // pair mode: subtree queue between wavefronts
+    int* qctl;                      // queue control words (zero at launch)
+    int* qready;                    // per ring slot (zero at launch): g*cap free for the producer of
+                                    // generation g, g*cap + 1 written, (g+1)*cap read
+    unsigned int* qitems;           // kItemWords per item
+    int* flags;                     // bit 1: queue stalled
 };
 
 // Batched counts: the lanes' partial counts of one root belong to one graph; add
@@ -103,18 +115,20 @@ __device__ __forceinline__ unsigned int leaf_edges(const unsigned int (&Y)[MAXW]
 // and no task is left.  acc / nodes / wsum / iters accumulate per lane.
 template <int MW, bool EC, bool PAIR, bool STATS>
 __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, int s, int slot, bool helping,
+                                          const unsigned int* item, int item_p, bool fresh,
                                           const int* S, unsigned int* B, int* pre, unsigned int* mbox,
                                           unsigned int* stk, int* tctr, int* ttot, unsigned long long lt,
                                           unsigned long long& acc, unsigned long long& nodes,
-                                          unsigned long long& wsum, unsigned long long& iters) {
+                                          unsigned long long& wsum, unsigned long long& iters,
+                                          unsigned long long& exps) {
     constexpr int STRIDE = b_stride_of(MW);
     constexpr int SLOT = MW + 1;                    // saved level: R words + p
     const int lane = __lane_id();
-    extract_rows<1, false>(s, P.row_ptr, P.col, lane, S, B, STRIDE);
+    if (fresh) extract_rows<1, false>(s, P.row_ptr, P.col, lane, S, B, STRIDE);
     const unsigned long long W = static_cast<unsigned long long>((s + 31) >> 5);
 
-    int total = s;                                   // tasks of this root
-    if (PAIR) {
+    int total = item ? 0 : s;                        // tasks of this root
+    if (PAIR && !item) {
         // pre[i] = number of pair tasks before row i
         int run = 0;
         for (int b0 = 0; b0 < s; b0 += 64) {
@@ -147,7 +161,16 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
 #pragma unroll
     for (int t = 0; t < MW; t++) R[t] = 0u;        // words >= Wr stay zero for this root
     int p = 0, depth = 0, sbase = 0;
-    bool out = false;                                // no task left for this lane
+    bool out = item != nullptr;                      // no task left for this lane
+    if (item && lane == 0) {
+        // a queued subtree: lane 0 starts from its candidate set, the others
+        // receive work by donation
+#pragma unroll
+        for (int t = 0; t < MW; t++) R[t] = item[4 + t];
+        p = item_p;
+    }
+    const bool steal = PAIR && P.steal && P.counts[P.list] < 2 * static_cast<int>(gridDim.x);
+    int chk = 0;
     int next_task = 0;                               // vertex tasks: wave counter
     int tq = 0, tq_end = 0;                          // pair tasks: claimed, unassigned range
     bool pq_done = false;                            // pair tasks: root counter exhausted
@@ -173,7 +196,9 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
             const int rank = __popcll(needy & lt);
             int t0 = 0, give = 0;
             bool exhausted = false;
-            if (PAIR) {
+            if (item) {
+                exhausted = true;
+            } else if (PAIR) {
                 // pair tasks: claim whole chunks from the root's global counter
                 // only when the wavefront-local range is empty, then hand them out
                 if (tq == tq_end && !pq_done) {
@@ -292,6 +317,62 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
             }
             wave_sync_lds();
         }
+        // subtree queue: when wavefronts wait for work (more than are queued),
+        // hand over the shallowest saved levels of up to kStealMax lanes
+        if (steal && ++chk == kStealEvery) {
+            chk = 0;
+            int want = 0;
+            if (lane == 0) {
+                want = ld_acquire(&P.qctl[Q_HUNGRY]);
+                if (want > 0) want -= ld_acquire(&P.qctl[Q_TAIL]) - ld_acquire(&P.qctl[Q_HEAD]);
+            }
+            want = __shfl(want, 0);
+            const unsigned long long dm = __ballot(depth > sbase);
+            int n = min(min(want, __popcll(dm)), kStealMax);
+            if (n > 0) {
+                int t0 = -1;
+                if (lane == 0) {
+                    // reserve n consecutive items while the ring has room
+                    // (items below head are claimed; their slots free up once read)
+                    const int h = ld_acquire(&P.qctl[Q_HEAD]);
+                    int t = ld_acquire(&P.qctl[Q_TAIL]);
+                    for (;;) {
+                        if (t + n - h > kQueueCap) { t = -1; break; }
+                        const int prev = atomicCAS(&P.qctl[Q_TAIL], t, t + n);
+                        if (prev == t) break;
+                        t = prev;
+                    }
+                    if (t >= 0) atomicAdd(&P.qctl[Q_PENDING], n);
+                    t0 = t;
+                }
+                t0 = __shfl(t0, 0);
+                if (t0 >= 0 && depth > sbase) {
+                    const int rd = __popcll(dm & lt);
+                    if (rd < n) {
+                        const int idx = t0 + rd;
+                        const int qs = idx & (kQueueCap - 1);
+                        const int gen = idx - qs;           // ring generation x capacity
+                        unsigned int* it = P.qitems + static_cast<size_t>(qs) * kItemWords;
+                        // wait until the slot's item of the previous generation has been read
+                        int spins = 0;
+                        while (__hip_atomic_load(&P.qready[qs], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen &&
+                               ++spins <= kReadySpins)
+                            __builtin_amdgcn_s_sleep(2);
+                        if (spins > kReadySpins) {
+                            atomicOr(P.flags, 2);
+                        } else {
+                            const unsigned int* f = stk + sbase * SLOT * 64 + lane;
+                            it[0] = static_cast<unsigned int>(slot);
+                            it[1] = f[MW * 64];
+#pragma unroll
+                            for (int t = 0; t < MW; t++) it[4 + t] = f[t * 64];
+                            __hip_atomic_store(&P.qready[qs], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        sbase++;
+                    }
+                }
+            }
+        }
         // done with this root when no lane holds work and no task is left
         bool busy = false;
 #pragma unroll
@@ -303,6 +384,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
 #pragma unroll
             for (int t = 0; t < MW; t++) has |= R[t] != 0u;
             if (has) {
+                if (STATS) exps += 1;
                 // expand the lowest candidate v
                 int v = 0;
                 bool got = false;
@@ -351,6 +433,48 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
     }
 }
 
+// Extract root `slot` of this list into LDS and walk it with rows of the
+// smallest supported width that holds its S.  item: a queued subtree of this
+// root (path length item_p) instead of the root's own tasks.
+template <int MAXW, bool EC, bool PAIR, bool STATS>
+__device__ __forceinline__ void run_root(const LaneParams& P, const int* roots, int k, int p0, int slot,
+                                         bool helping, const unsigned int* item, int item_p, bool cached, int* ctl, int* S,
+                                         unsigned int* B, int* pre, unsigned int* mbox, unsigned int* stk, int* tctr,
+                                         int* ttot, unsigned long long lt, unsigned long long& acc,
+                                         unsigned long long& nodes, unsigned long long& wsum,
+                                         unsigned long long& iters, unsigned long long& exps) {
+    // cached: S and the rows of this root are still in LDS from the previous walk
+    if (!cached) extract_set<1, EC>(roots[slot], P.row_ptr, P.col, P.src, __lane_id(), S, &ctl[1]);
+    const int s = ctl[1];
+    if (EC && k == 3) {
+        if (__lane_id() == 0 && !helping) acc += static_cast<unsigned long long>(s);
+        return;
+    }
+#define KC_WALK(MW)                                                                                          \
+    walk_root<MW, EC, PAIR, STATS>(P, k, p0, s, slot, helping, item, item_p, !cached, S, B, pre, mbox, stk, tctr, ttot, lt, \
+                                   acc, nodes, wsum, iters, exps)
+    const int Wr = __builtin_amdgcn_readfirstlane((s + 31) >> 5);
+    if constexpr (MAXW >= 32) {
+        if (Wr > 16) { KC_WALK(32); return; }
+    }
+    if constexpr (MAXW >= 16) {
+        if (Wr > 8) { KC_WALK(16); return; }
+    }
+    if constexpr (MAXW >= 8) {
+        if (Wr > 6) { KC_WALK(8); return; }
+        if (Wr > 4) { KC_WALK(6); return; }
+    }
+    if constexpr (MAXW >= 4) {
+        if (Wr > 3) { KC_WALK(4); return; }
+        if (Wr > 2) { KC_WALK(3); return; }
+    }
+    if constexpr (MAXW >= 2) {
+        if (Wr > 1) { KC_WALK(2); return; }
+    }
+    KC_WALK(1);
+#undef KC_WALK
+}
+
 // MAXW: bitset words per row of this root list; EC: edge roots; PAIR: pair
 // tasks + helping (deep trees on wide roots); STATS: count expanded nodes.
 template <int MAXW, bool EC, bool PAIR, bool STATS>
@@ -377,15 +501,24 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
     int* ttot = P.task_tot + list_off;
     const int nwaves = gridDim.x;                   // one wavefront per block
     const unsigned long long lt = lanemask_lt();
+    // hand subtrees between wavefronts only where roots are scarce (under two per
+    // wavefront): with many roots the walks balance by themselves and handoff
+    // latency would only lengthen the critical path
+    const bool steal = PAIR && P.steal && nroots < 2 * nwaves;
+    int* q = P.qctl;
+    int cur = -1;                                   // root whose S and rows are in LDS
 
-    unsigned long long acc = 0, nodes = 0, wsum = 0, iters = 0;
+    // an earlier launch of the same call stalled: give up at once
+    if (steal && (ld_acquire(P.flags) & 2)) return;
+    unsigned long long acc = 0, nodes = 0, wsum = 0, iters = 0, exps = 0, idle = 0;
     const unsigned long long t_begin = STATS ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    if (steal && lane == 0) atomicAdd(&q[Q_ROOTING], 1);    // in the root phase
     bool helping = false;
     int rq = 0, rq_end = 0;                         // claimed, unprocessed root range
     constexpr int RC = PAIR ? 1 : kRootChunk;
 
+    // ---------------------------------------------- root phase
     for (;;) {
-        // ---------------------------------------------------------- root
         int slot = -1;
         if (!helping) {
             if (rq == rq_end) {
@@ -421,41 +554,107 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
             if (best == 0ull) break;
             slot = static_cast<int>(best & 0xffffffffu);
         }
-        const int rid = roots[slot];
-        const int graph = P.gacc ? P.gid[EC ? P.src[rid] : rid] : 0;
-        extract_set<1, EC>(rid, P.row_ptr, P.col, P.src, lane, S, &ctl[1]);
-        const int s = ctl[1];
-        if (EC && k == 3) {
-            if (lane == 0 && !helping) acc += static_cast<unsigned long long>(s);
-            if (P.gacc) flush_root(P, graph, acc);
-            wave_sync_lds();
-            continue;
-        }
-        // rows padded only to the smallest supported width holding this root
-        const int Wr = __builtin_amdgcn_readfirstlane((s + 31) >> 5);
-        if constexpr (MAXW >= 32) {
-            if (Wr > 16) { walk_root<32, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
-        }
-        if constexpr (MAXW >= 16) {
-            if (Wr > 8) { walk_root<16, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
-        }
-        if constexpr (MAXW >= 8) {
-            if (Wr > 6) { walk_root<8, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
-            if (Wr > 4) { walk_root<6, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
-        }
-        if constexpr (MAXW >= 4) {
-            if (Wr > 3) { walk_root<4, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
-            if (Wr > 2) { walk_root<3, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
-        }
-        if constexpr (MAXW >= 2) {
-            if (Wr > 1) { walk_root<2, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters); goto root_done; }
-        }
-        walk_root<1, EC, PAIR, STATS>(P, k, p0, s, slot, helping, S, B, pre, mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters);
-    root_done:
+        const int graph = P.gacc ? P.gid[EC ? P.src[roots[slot]] : roots[slot]] : 0;
+        run_root<MAXW, EC, PAIR, STATS>(P, roots, k, p0, slot, helping, nullptr, 0, false, ctl, S, B, pre, mbox, stk,
+                                        tctr, ttot, lt, acc, nodes, wsum, iters, exps);
+        cur = slot;
         if (PAIR && !helping && lane == 0)
             __hip_atomic_store(&P.active[blockIdx.x], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (P.gacc) flush_root(P, graph, acc);
         wave_sync_lds();
+    }
+
+    // ---------------------------------------------- queue phase
+    // Subtrees that busy wavefronts handed over (see walk_root).  The launch is
+    // finished when no wavefront is in the root phase and no queued subtree is
+    // unfinished; `pending` counts subtrees from publication to completion, so
+    // both reading zero (rooting first) means no work can appear any more.
+    if (steal) {
+        if (lane == 0) __hip_atomic_fetch_add(&q[Q_ROOTING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        bool hungry = false;
+        unsigned long long sig = ~0ull, t_sig = 0, t_idle = 0;
+        bool idling = false;
+        int backoff = 0;                            // empty polls in a row (sleep grows with it)
+        for (;;) {
+            int idx = -1, state = 0;                // state 1: finished, 2: stalled
+            if (lane == 0) {
+                const int h = ld_acquire(&q[Q_HEAD]);
+                const int t = ld_acquire(&q[Q_TAIL]);
+                if (h < t) {
+                    if (atomicCAS(&q[Q_HEAD], h, h + 1) == h) idx = h;
+                } else {
+                    const int rooting = __hip_atomic_load(&q[Q_ROOTING], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    const int pend = __hip_atomic_load(&q[Q_PENDING], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+                    const unsigned long long sg = (static_cast<unsigned long long>(static_cast<unsigned int>(t)) << 40) ^
+                                                  (static_cast<unsigned long long>(static_cast<unsigned int>(pend)) << 20) ^
+                                                  static_cast<unsigned int>(rooting);
+                    if (sg != sig) { sig = sg; t_sig = now; }
+                    if ((rooting == 0 && pend == 0) || (ld_acquire(P.flags) & 2)) state = 1;
+                    else if (now - t_sig > kStallTicks) state = 2;
+                }
+            }
+            idx = __shfl(idx, 0);
+            state = __shfl(state, 0);
+            if (STATS && idling && (idx >= 0 || state != 0)) {
+                idle += __builtin_amdgcn_s_memrealtime() - t_idle;
+                idling = false;
+            }
+            if (idx >= 0) {
+                if (hungry && lane == 0) atomicAdd(&q[Q_HUNGRY], -1);
+                hungry = false;
+                backoff = 0;
+                // the producer reserved this item and is writing it: wait for its flag
+                // the slot reads gen + 1 once the producer of item idx has written it
+                int ok = 1, slot = 0, ip = 0;
+                const int qs = idx & (kQueueCap - 1);
+                const int gen = idx - qs;
+                const unsigned int* it = P.qitems + static_cast<size_t>(qs) * kItemWords;
+                if (lane == 0) {
+                    int spins = 0;
+                    while (__hip_atomic_load(&P.qready[qs], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen + 1) {
+                        if (++spins > kReadySpins) { ok = 0; break; }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+                ok = __shfl(ok, 0);
+                if (!ok) {
+                    if (lane == 0) atomicOr(P.flags, 2);
+                    break;
+                }
+                // copy the item into LDS (the pair-task prefix area, unused for a
+                // queued subtree) and free the slot for its next producer
+                unsigned int* ibuf = reinterpret_cast<unsigned int*>(pre);
+                if (lane < 4 + MAXW) ibuf[lane] = ld_acquire(&it[lane]);
+                wave_sync_lds();
+                if (lane == 0)   // next generation's producer may write the slot
+                    __hip_atomic_store(&P.qready[qs], gen + kQueueCap, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                slot = static_cast<int>(ibuf[0]);
+                ip = static_cast<int>(ibuf[1]);
+                run_root<MAXW, EC, PAIR, STATS>(P, roots, k, p0, slot, true, ibuf, ip, slot == cur, ctl, S, B, pre,
+                                                mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters, exps);
+                cur = slot;
+                wave_sync_lds();
+                if (lane == 0) __hip_atomic_fetch_add(&q[Q_PENDING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                continue;
+            }
+            if (state == 1) break;
+            if (state == 2) {
+                if (lane == 0) atomicOr(P.flags, 2);
+                break;
+            }
+            if (!hungry && lane == 0) atomicAdd(&q[Q_HUNGRY], 1);
+            hungry = true;
+            if (STATS && !idling) {
+                t_idle = __builtin_amdgcn_s_memrealtime();
+                idling = true;
+            }
+            // back off: 1, 2, 4, .. 32 sleeps of 127 x 64 clocks between polls,
+            // so that waiting wavefronts do not crowd the queue words
+            if (backoff < 5) backoff++;
+            for (int i = 0; i < (1 << backoff); i++) __builtin_amdgcn_s_sleep(127);
+        }
+        if (hungry && lane == 0) atomicAdd(&q[Q_HUNGRY], -1);
     }
 
     unsigned long long lo, hi;
@@ -464,14 +663,16 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
     if (STATS) {
         nodes = wave_sum(nodes);
         wsum = wave_sum(wsum);
+        exps = wave_sum(exps);
         if (lane == 0) {
             atomicAdd(P.stats, nodes);
             atomicAdd(P.stats + 1, wsum);
             atomicAdd(P.iters, iters);
-            // busy time of this wavefront and the span of the whole grid
-            // (100 MHz constant clock): [sum of busy, min start, max end]
+            atomicAdd(P.iters + 1, exps);
+            // busy time of this wavefront (queue waits excluded) and the span of
+            // the whole grid (100 MHz constant clock): [sum of busy, min start, max end]
             const unsigned long long t_end = __builtin_amdgcn_s_memrealtime();
-            atomicAdd(P.timing, t_end - t_begin);
+            atomicAdd(P.timing, t_end - t_begin - idle);
             atomicMin(P.timing + 1, t_begin);
             atomicMax(P.timing + 2, t_end);
         }
@@ -511,6 +712,7 @@ int launch_lane_m(const LaneParams& P, bool ec, bool pair, bool stats, int* g, h
 }  // namespace
 
 int lane_launch(const LaneLaunch& L, hipStream_t s) {
+    if (L.pair && L.maxw < 2) return KC_EINVAL;    // pair mode keeps queued items in the prefix area
     LaneParams P;
     P.k = L.k;
     P.row_ptr = L.row_ptr;
@@ -529,6 +731,11 @@ int lane_launch(const LaneLaunch& L, hipStream_t s) {
     P.timing = L.timing_ptr;
     P.gacc = L.gacc;
     P.gid = L.gid;
+    P.steal = L.pair && L.steal;
+    P.qctl = L.qctl;
+    P.qready = L.qready;
+    P.qitems = L.qitems;
+    P.flags = L.flags;
     const int p0 = L.ec ? 3 : 2;
     // pair tasks start at path length p0 + 1; vertex tasks at p0.  Saved levels
     // are needed for path lengths below k - 2.
