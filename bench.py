@@ -335,16 +335,19 @@ def main():
                          "width_list_ms": [round(x, 3) for x in mw],
                          "width_list_roots": [int(ps[0].roots_width[j]) for j in range(6)],
                          "width_list_handoffs": [int(ps[-1].items_width[j]) for j in range(6)]}
-        for j in range(6):
-            phases.append((mw[j], k, j))
+        phases.append((ms, k, mw))
 
-    # dominant kernel launch (one width list at one k) and its algorithmic work,
-    # from a separate, untimed stats pass of the same call
-    dom_ms, dom_k, dom_j = max(phases)
+    # dominant kernel launch: at the k that takes longest, the width-list launch
+    # with the most wavefront time (launch span x busy fraction; the widest list
+    # runs beside the others, so its span alone overstates it), and its
+    # algorithmic work, from a separate, untimed stats pass of the same call
+    _, dom_k, dom_mw = max(phases)
     sp = kc.Profile()
     c_stats = kc.count(dag, dom_k, scheme=args.scheme, width=args.width, ws=cws, profile=sp, collect_stats=True,
                        handoff=not args.no_handoff)
     assert c_stats == counts[dom_k]
+    dom_j = max(range(6), key=lambda j: dom_mw[j] * float(sp.busy_width[j]))
+    dom_ms = dom_mw[dom_j]
     work_ops = 2.0 * sp.words_width[dom_j]
     achieved = work_ops / (dom_ms / 1e3) / 1e12
     roofline = {

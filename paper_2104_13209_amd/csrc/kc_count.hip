@@ -485,7 +485,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         if (lane_lds_bytes(1 << top, k, ec, deep && top >= 1) > 160 * 1024) lane_path = false;
     }
     if (lane_path) {
-        KC_CHECK(hipMemsetAsync(w.active, 0xff, sizeof(int) * w.nactive, s));
+        KC_CHECK(hipMemsetAsync(w.active, 0xff, 2 * sizeof(int) * w.nactive, s));
         if (k >= (ec ? 3 : 2) + 4) {
             KC_CHECK(hipMemsetAsync(w.task_ctr, 0, sizeof(int) * static_cast<size_t>(nroots), s));
             KC_CHECK(hipMemsetAsync(w.task_tot, 0, sizeof(int) * static_cast<size_t>(nroots), s));
@@ -519,7 +519,19 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         const bool deep = k >= p0 + 4;
         int top = 0;
         while (top < kWidthLists - 1 && (32 << top) < d->d_max) top++;
+        // deep trees: the widest list runs on a side stream beside the others, so
+        // that the tail of its few large roots overlaps their work
+        SideGuard side;
+        if (deep && top >= 1) {
+            st = side_acquire(&side.s);
+            if (st != KC_OK) return st;
+            side.held = true;
+            KC_CHECK(hipEventRecord(side.s.fork, s));
+            KC_CHECK(hipStreamWaitEvent(side.s.stream, side.s.fork, 0));
+        }
         for (int lst = top; lst >= 0; lst--) {
+            const bool on_side = side.held && lst == top;
+            hipStream_t ls = on_side ? side.s.stream : s;
             if (lst == 1 && prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
             LaneLaunch L;
             L.k = k;
@@ -536,7 +548,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.head = w.ctl + CC_WH0 + lst;
             L.task_ctr = w.task_ctr;
             L.task_tot = w.task_tot;
-            L.active = w.active;
+            L.active = on_side ? w.active + w.nactive : w.active;
             L.acc = w.acc;
             L.stats_ptr = w.acc + 6 + 2 * lst;
             L.iters_ptr = w.acc + 6 + 2 * kWidthLists + 2 * lst;
@@ -544,13 +556,17 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.steal = L.pair && !(o && o->no_handoff);
             L.qctl = w.qctl + kQueueCtlWords * lst;
             L.qready = w.qready + static_cast<size_t>(kQueueCap) * lst;
-            L.qitems = w.qitems;
+            L.qitems = w.qitems + (on_side ? static_cast<size_t>(kQueueCap) * kItemWords : 0);
             L.flags = w.ctl + CC_FLAGS;
-            if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst], s));
+            if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst], ls));
             L.grid_out = &lane_grid[lst];
-            st = lane_launch(L, s);
+            st = lane_launch(L, ls);
             if (st != KC_OK) return st;
-            if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst + 1], s));
+            if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst + 1], ls));
+        }
+        if (side.held) {
+            KC_CHECK(hipEventRecord(side.s.join, side.s.stream));
+            KC_CHECK(hipStreamWaitEvent(s, side.s.join, 0));
         }
         if (prof && top < 1) KC_CHECK(hipEventRecord(pe->ev[2], s));
         if (prof)

@@ -62,10 +62,10 @@ struct CountWs {
     unsigned int* gstack;         // heavy pivot stacks, one slab per resident wavefront
     int* task_ctr;                // lane walk, pair tasks: claimed tasks per root
     int* task_tot;                // lane walk, pair tasks: total tasks + 1 per root (0 = unpublished)
-    int* active;                  // lane walk: root slot owned by each wavefront (-1 = none)
+    int* active;                  // lane walk: root slot owned by each wavefront (-1 = none), main + side
     int* qctl;                    // lane walk, subtree queue: kQueueCtlWords per width list
     int* qready;                  // lane walk, subtree queue: slot sequence words, kQueueCap per width list
-    unsigned int* qitems;         // lane walk, subtree queue: kItemWords per item
+    unsigned int* qitems;         // lane walk, subtree queue: kItemWords per slot, main + side
     int nactive;
     int binom_n;
     size_t slab_words;
@@ -83,10 +83,10 @@ inline CountWs carve_count(void* ws, const kc_dag* d, bool pivot, size_t* bytes)
     w.task_ctr = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
     w.task_tot = c.take<int>(static_cast<size_t>(nr > 0 ? nr : 1));
     w.nactive = device_cus() * kLaneWavesPerCU;
-    w.active = c.take<int>(static_cast<size_t>(w.nactive));
+    w.active = c.take<int>(2 * static_cast<size_t>(w.nactive));    // main and side stream
     w.qctl = c.take<int>(kQueueCtlWords * kWidthLists);
     w.qready = c.take<int>(static_cast<size_t>(kQueueCap) * kWidthLists);
-    w.qitems = c.take<unsigned int>(static_cast<size_t>(kQueueCap) * kItemWords);
+    w.qitems = c.take<unsigned int>(2 * static_cast<size_t>(kQueueCap) * kItemWords);   // main and side stream
     if (pivot) {
         const int s_cap = s_cap_for(d->d_max);
         w.binom_n = s_cap + 2;

@@ -36,6 +36,28 @@ inline int div_up(long long a, long long b) { return static_cast<int>((a + b - 1
 // Number of compute units of the current device (cached per process).
 int device_cus();
 
+// An auxiliary stream (default priority) with two timing-free events, taken
+// from a per-device pool for the length of one call, so that one launch of the
+// call can run beside the others (fork: record on the caller's stream, wait on
+// the side stream; join: the reverse).  Entries are created on first use and
+// kept for the life of the process.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    int device = -1;
+};
+int side_acquire(SideStream* out);      // KC_OK or KC_EDEVICE
+void side_release(const SideStream& s);
+
+// Returns a held side stream to the pool at scope exit.
+struct SideGuard {
+    SideStream s;
+    bool held = false;
+    ~SideGuard() {
+        if (held) side_release(s);
+    }
+};
+
 // ------------------------------------------------------------- device side
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

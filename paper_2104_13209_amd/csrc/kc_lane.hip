@@ -31,6 +31,7 @@ constexpr int kPairChunk = 64;    // pair tasks claimed per global atomic
 constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
 constexpr int kStealEvery = 128;  // loop iterations between looks at the subtree queue
 constexpr int kStealMax = 8;      // subtrees handed over per look
+constexpr int kMaxWaiters = 256;  // wavefronts that wait for handed-over subtrees; the rest leave
 // queue control words
 constexpr int Q_HEAD = 0, Q_TAIL = 1, Q_PENDING = 2, Q_ROOTING = 3, Q_HUNGRY = 4;
 constexpr unsigned long long kStallTicks = 2000000000ull;   // 20 s at 100 MHz without queue progress
@@ -571,11 +572,20 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
     // both reading zero (rooting first) means no work can appear any more.
     if (steal) {
         if (lane == 0) __hip_atomic_fetch_add(&q[Q_ROOTING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        bool hungry = false;
+        // at most kMaxWaiters wavefronts wait; the others end here and free their
+        // compute unit slots for launches that run beside this one.  A waiter
+        // leaves only at the end, so handed-over subtrees always find one.
+        int stay = 1;
+        if (lane == 0 && atomicAdd(&q[Q_HUNGRY], 1) >= kMaxWaiters) {
+            atomicAdd(&q[Q_HUNGRY], -1);
+            stay = 0;
+        }
+        stay = __shfl(stay, 0);
+        bool hungry = stay != 0;
         unsigned long long sig = ~0ull, t_sig = 0, t_idle = 0;
         bool idling = false;
         int backoff = 0;                            // empty polls in a row (sleep grows with it)
-        for (;;) {
+        while (stay) {
             int idx = -1, state = 0;                // state 1: finished, 2: stalled
             if (lane == 0) {
                 const int h = ld_acquire(&q[Q_HEAD]);

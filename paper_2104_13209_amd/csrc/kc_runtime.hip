@@ -1,4 +1,9 @@
-// Process-wide runtime helpers of libkc: device properties and status text.
+// Process-wide runtime helpers of libkc: device properties, the side-stream
+// pool and status text.
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "kc_internal.h"
 
 namespace kc {
@@ -16,6 +21,41 @@ int device_cus() {
         cached_dev = dev;
     }
     return cached_cus;
+}
+
+namespace {
+std::mutex g_side_mu;
+std::map<int, std::vector<SideStream>> g_side_free;   // per device
+}  // namespace
+
+int side_acquire(SideStream* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KC_EDEVICE;
+    {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        auto& v = g_side_free[dev];
+        if (!v.empty()) {
+            *out = v.back();
+            v.pop_back();
+            return KC_OK;
+        }
+    }
+    SideStream s;
+    s.device = dev;
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return KC_EDEVICE;
+    if (hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s.join, hipEventDisableTiming) != hipSuccess) {
+        if (s.fork) (void)hipEventDestroy(s.fork);
+        (void)hipStreamDestroy(s.stream);
+        return KC_EDEVICE;
+    }
+    *out = s;
+    return KC_OK;
+}
+
+void side_release(const SideStream& s) {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    g_side_free[s.device].push_back(s);
 }
 
 }  // namespace kc
