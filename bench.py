@@ -37,6 +37,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(k, width_list):
+    """HBM bytes of one lane-walk launch (width list, k) from the committed
+    FETCH_SIZE / WRITE_SIZE record, or None when there is none or the native
+    sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(here, "paper_2104_13209_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(os.path.join(here, "profiles", "k_lane_powerlaw_k10_hbm_counters.md")) as fh:
+            line = next(x for x in fh if x.startswith("traffic-record: "))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line[len("traffic-record: "):])
+    if rec.get("csrc_sha256") != h.hexdigest() or rec.get("k") != k:
+        return None
+    b = rec["bytes_per_launch_by_width_list"].get(str(width_list))
+    return int(b) if b is not None else None
+
+
 def cpu_baseline(g, ks, frac, seed=0):
     """The oracle (single thread) on a bounded sample: full degeneracy orientation,
     then every k over a random fraction of the edge roots, scaled to all roots."""
@@ -358,7 +382,8 @@ def main():
         "peak": round(VALU_PEAK_TOPS, 2),
         "unit": "TOP/s",
         "frac": round(achieved / VALU_PEAK_TOPS, 5),
-        "traffic": None,
+        "traffic": measured_traffic(dom_k, dom_j),
+        "traffic_source": "FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy-calibrated) for this launch; profiles/k_lane_powerlaw_k10_hbm_counters.md",
         "work": "2 int32 ops (AND + popcount) per bitset word per expanded tree node: "
                 "%d nodes with rows of at most %d words (the root's own word count each) = %d words in one "
                 "launch of %.3f ms (HIP events, mean of timed steps)"
