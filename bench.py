@@ -320,19 +320,28 @@ def main():
     cws = torch.empty(kc.count_workspace_bytes(dag, max(ks), False, args.scheme), dtype=torch.uint8, device=dev)
     log("dag: d_max=%d degeneracy=%d" % (dag.d_max, dag.degeneracy))
 
+    orient_ms = []
+
     def step(profiles):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         kc.orient(csr, order, validate=True, ws=ows, out=dag)
+        e1.record()
+        e1.synchronize()
+        if profiles is not None:
+            orient_ms.append(e0.elapsed_time(e1))
         out = {}
         for k in ks:
             p = kc.Profile()
             out[k] = kc.count(dag, k, scheme=args.scheme, width=args.width, ws=cws, profile=p,
                               handoff=not args.no_handoff)
-            profiles.setdefault(k, []).append(p)
+            if profiles is not None:
+                profiles.setdefault(k, []).append(p)
         return out
 
     for i in range(args.warmup):
         t0 = time.perf_counter()
-        counts = step({})
+        counts = step(None)
         log("warmup %d: %.3f s counts=%s" % (i, time.perf_counter() - t0, counts))
 
     profiles = {}
@@ -434,6 +443,7 @@ def main():
             "ks": ks, "order": "degeneracy", "scheme": "EC" if args.scheme == 2 else "VC",
             "validate": True,
         },
+        "orient_ms": round(sum(orient_ms) / max(1, len(orient_ms)), 3),
         "per_k": per_k,
         "roofline": roofline,
         "cpu_baseline": cpu,

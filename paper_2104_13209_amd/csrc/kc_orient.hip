@@ -89,6 +89,42 @@ __global__ void __launch_bounds__(kBlock) k_degree_key(int n, const int* __restr
     if ((threadIdx.x & 63) == 0) atomicMax(&ctl[CTL_MAXKEY], mx);
 }
 
+// Appends the flagged lanes' values to list[] with one atomic per wavefront.
+__device__ __forceinline__ void append_wave(bool flag, int v, int* list, int* size, int lane) {
+    const unsigned long long m = __ballot(flag);
+    if (m == 0ull) return;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(size, __popcll(m));
+    base = __shfl(base, 0);
+    if (flag) list[base + __popcll(m & lanemask_lt())] = v;
+}
+
+// One peeling round: the frontier's vertices get round r, and every live
+// neighbour loses one degree; a neighbour that drops to the level c joins the
+// next frontier.  Wavefront wave of nwaves takes frontier entries wave, wave +
+// nwaves, ...; its lanes split the vertex's row.
+__device__ __forceinline__ void peel_round(int r, int c, const int* cur, int fsize, int* nxt, int* nsize,
+                                           const int* __restrict__ row_ptr, const int* __restrict__ col, int* deg,
+                                           int* rnd, int wave, int nwaves, int lane) {
+    for (int fi = wave; fi < fsize; fi += nwaves) {
+        const int v = ld_acquire(&cur[fi]);
+        if (lane == 0) rnd[v] = r;
+        const int b = row_ptr[v], e = row_ptr[v + 1];
+        for (int j0 = b; j0 < e; j0 += 64) {
+            const int j = j0 + lane;
+            bool hit = false;
+            int w = 0;
+            if (j < e) {
+                w = col[j];
+                // a stale read of a vertex removed earlier only decrements a dead
+                // degree, which never equals c + 1 any more
+                if (ld_acquire(&rnd[w]) < 0) hit = atomicSub(&deg[w], 1) == c + 1;
+            }
+            append_wave(hit, w, nxt, nsize, lane);
+        }
+    }
+}
+
 // Degeneracy order by level-synchronous peeling (the paper only states that its
 // k-core decomposition runs on the GPU; this schedule is ours).
 //
@@ -100,6 +136,11 @@ __global__ void __launch_bounds__(kBlock) k_degree_key(int n, const int* __restr
 // r at level c had at most c live neighbours at the start of round r, and its
 // out-neighbours under the (round, id) order are among them, so the out-degree
 // is bounded by the degeneracy (the largest level).
+//
+// One pass collects both the vertices of degree <= c + 1 and the minimum live
+// degree, since the next level is almost always c + 1; a second pass runs only
+// when no live vertex has that degree.  Frontier appends take one atomic per
+// wavefront.
 __global__ void __launch_bounds__(kBlock) k_peel(int n, const int* __restrict__ row_ptr,
                                                 const int* __restrict__ col, int* deg, int* rnd,
                                                 int* fr0, int* fr1, int* val, int* ctl) {
@@ -127,38 +168,45 @@ __global__ void __launch_bounds__(kBlock) k_peel(int n, const int* __restrict__ 
         int* nxt = (r & 1) ? fr0 : fr1;
         int* csize = &ctl[CTL_SIZE0 + r % 3];
         int* nsize = &ctl[CTL_SIZE0 + (r + 1) % 3];
-        int fsize = ld_acquire(csize);
+        const int fsize = ld_acquire(csize);
         if (fsize == 0) {
+            // Level change, as an empty round r: the next frontier is collected
+            // into nxt (no block reads nsize or nxt while others may still be
+            // reading csize above), then round r + 1 peels it.  One pass takes
+            // the live vertices of degree <= c + 1 and the minimum live degree.
+            if (tid == 0) ctl[CTL_SIZE0 + (r + 2) % 3] = 0;
             int mn = INT_MAX;
-            for (int v = tid; v < n; v += nth)
-                if (ld_acquire(&rnd[v]) < 0) {
-                    int d = ld_acquire(&deg[v]);
+            for (int b0 = tid - lane; b0 < n; b0 += nth) {
+                const int v = b0 + lane;
+                bool in = false;
+                if (v < n && ld_acquire(&rnd[v]) < 0) {
+                    const int d = ld_acquire(&deg[v]);
                     mn = d < mn ? d : mn;
+                    in = d <= c + 1;
                 }
+                append_wave(in, v, nxt, nsize, lane);
+            }
             mn = wave_min(mn);
             if (lane == 0 && mn != INT_MAX) atomicMin(&ctl[CTL_MIN], mn);
             grid.sync();
-            c = ld_acquire(&ctl[CTL_MIN]);
-            for (int v = tid; v < n; v += nth)
-                if (ld_acquire(&rnd[v]) < 0 && ld_acquire(&deg[v]) <= c) cur[atomicAdd(csize, 1)] = v;
-            grid.sync();
-            fsize = ld_acquire(csize);
-            if (tid == 0) ctl[CTL_MIN] = INT_MAX;
+            if (ld_acquire(nsize) > 0) {
+                c = c + 1;          // the minimum live degree is c + 1
+            } else {
+                c = ld_acquire(&ctl[CTL_MIN]);
+                for (int b0 = tid - lane; b0 < n; b0 += nth) {
+                    const int v = b0 + lane;
+                    const bool in = v < n && ld_acquire(&rnd[v]) < 0 && ld_acquire(&deg[v]) <= c;
+                    append_wave(in, v, nxt, nsize, lane);
+                }
+                grid.sync();
+            }
+            if (tid == 0) ctl[CTL_MIN] = INT_MAX;   // every read of it is behind the last barrier
             degen = c > degen ? c : degen;
+            r++;
+            continue;
         }
         if (tid == 0) ctl[CTL_SIZE0 + (r + 2) % 3] = 0;
-        for (int fi = wave; fi < fsize; fi += nwaves) {
-            int v = ld_acquire(&cur[fi]);
-            if (lane == 0) rnd[v] = r;
-            int b = row_ptr[v], e = row_ptr[v + 1];
-            for (int j = b + lane; j < e; j += 64) {
-                int w = col[j];
-                if (ld_acquire(&rnd[w]) < 0) {
-                    int old = atomicSub(&deg[w], 1);
-                    if (old == c + 1) nxt[atomicAdd(nsize, 1)] = w;
-                }
-            }
-        }
+        peel_round(r, c, cur, fsize, nxt, nsize, row_ptr, col, deg, rnd, wave, nwaves, lane);
         removed += fsize;
         r++;
         grid.sync();
@@ -546,7 +594,7 @@ extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out,
         int occ = 0;
         KC_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel, kBlock, 0));
         if (occ < 1) return KC_EDEVICE;
-        int blocks = device_cus() * (occ < 2 ? occ : 2);
+        int blocks = device_cus();   // one block per CU: a cheaper grid barrier per round
         int n_ = n;
         const int* rp = g->row_ptr;
         const int* cl = g->col;

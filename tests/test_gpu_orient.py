@@ -100,3 +100,21 @@ def test_validation_rejects_malformed(kc):
         with pytest.raises(kc.KcError) as e:
             kc.orient(dev, kc.ORDER_DEGREE, validate=True)
         assert e.value.code == kc.EINVAL
+
+
+def test_degeneracy_order_repeatable(kc):
+    """Repeated peels of the same graph into the same buffers give the identical
+    permutation (the schedule is deterministic: keys are (round, id))."""
+    import torch
+    g = synth.config_powerlaw(wmax=5657.0)
+    csr = kc.to_device(g)
+    ws = torch.empty(kc.orient_workspace_bytes(g.n, g.nnz, kc.ORDER_DEGENERACY), dtype=torch.uint8, device="cuda")
+    first = None
+    for _ in range(6):
+        d = kc.orient(csr, kc.ORDER_DEGENERACY, validate=True, ws=ws)
+        assert d.d_max <= d.degeneracy
+        perm = d.perm.cpu().numpy()
+        if first is None:
+            first = (perm, d.degeneracy, d.d_max)
+        else:
+            assert np.array_equal(perm, first[0]) and d.degeneracy == first[1] and d.d_max == first[2]
