@@ -37,6 +37,11 @@ inline int k_levels(int k, int first) {
 
 __host__ __device__ constexpr int b_stride_of(int maxw) { return (maxw > 1 && (maxw % 2) == 0) ? maxw + 1 : maxw; }
 
+// Row stride (words) of the lane walk's bitset rows.  Rows of up to 4 words keep
+// an odd stride and 32-bit reads (row starts spread over all banks); wider rows
+// are padded to a multiple of 4 words and read with 128-bit loads (6 -> 8).
+__host__ __device__ constexpr int lane_stride(int w) { return w <= 4 ? b_stride_of(w) : ((w + 3) & ~3); }
+
 // Bitset words per row used for a DAG of this d_max (rows of at most 32 * maxw bits).
 inline int maxw_for(int d_max) {
     if (d_max <= 64) return 2;
@@ -164,7 +169,7 @@ inline size_t lane_lds_bytes(int maxw, int k, bool ec, bool pair) {
     const int s_cap = 32 * maxw;
     const int slot = maxw + 1;
     const int first = (ec ? 3 : 2) + (pair ? 1 : 0);
-    const int words = 16 + s_cap + s_cap * b_stride_of(maxw) + (pair ? s_cap + 1 : 0) + 64 * slot +
+    const int words = 16 + s_cap + s_cap * lane_stride(maxw) + (pair ? s_cap + 1 : 0) + 64 * slot +
                       k_levels(k, first) * slot * 64;
     return static_cast<size_t>(words) * 4;
 }

@@ -94,21 +94,53 @@ __device__ __forceinline__ int select_bit(unsigned int x, int r) {
 // are upper triangular, so this counts every pair once in any visiting order,
 // and row x (word t) can skip the words below t.  This is the whole last level
 // of Fig. 2 under a node whose candidate set is Y, done in one tight loop.
-template <int MAXW, int STRIDE>
-__device__ __forceinline__ unsigned int leaf_edges(const unsigned int (&Y)[MAXW], const unsigned int* B) {
+template <int MW>
+__device__ __forceinline__ unsigned int leaf_edges(const unsigned int (&Y)[MW], const unsigned int* B) {
+    constexpr int STRIDE = lane_stride(MW);
     unsigned int c = 0;
 #pragma unroll
-    for (int t = 0; t < MAXW; t++) {
+    for (int t = 0; t < MW; t++) {
         unsigned int x = Y[t];
         while (x) {
             const int b = __ffs(x) - 1;
             x &= x - 1u;
             const unsigned int* row = B + (32 * t + b) * STRIDE;
+            if constexpr (STRIDE % 4 != 0) {
 #pragma unroll
-            for (int w = t; w < MAXW; w++) c += __popc(Y[w] & row[w]);
+                for (int w = t; w < MW; w++) c += __popc(Y[w] & row[w]);
+            } else {
+                // 128-bit reads from the quad holding word t on
+#pragma unroll
+                for (int q = t >> 2; q < (MW + 3) / 4; q++) {
+                    const uint4 r4 = *reinterpret_cast<const uint4*>(row + 4 * q);
+                    c += __popc(Y[4 * q] & r4.x);
+                    if (4 * q + 1 < MW) c += __popc(Y[4 * q + 1] & r4.y);
+                    if (4 * q + 2 < MW) c += __popc(Y[4 * q + 2] & r4.z);
+                    if (4 * q + 3 < MW) c += __popc(Y[4 * q + 3] & r4.w);
+                }
+            }
         }
     }
     return c;
+}
+
+// Words [0, MW) of a bitset row at stride lane_stride(MW): 32-bit reads for odd
+// strides, 128-bit reads when the stride is a multiple of 4 (16-byte aligned).
+template <int MW>
+__device__ __forceinline__ void load_row(const unsigned int* p, unsigned int (&x)[MW]) {
+    if constexpr (lane_stride(MW) % 4 != 0) {
+#pragma unroll
+        for (int i = 0; i < MW; i++) x[i] = p[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < (MW + 3) / 4; i++) {
+            const uint4 q = *reinterpret_cast<const uint4*>(p + 4 * i);
+            x[4 * i] = q.x;
+            if (4 * i + 1 < MW) x[4 * i + 1] = q.y;
+            if (4 * i + 2 < MW) x[4 * i + 2] = q.z;
+            if (4 * i + 3 < MW) x[4 * i + 3] = q.w;
+        }
+    }
 }
 
 // One root's traversal with rows of MW words (MW >= the root's word count):
@@ -122,7 +154,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                                           unsigned long long& acc, unsigned long long& nodes,
                                           unsigned long long& wsum, unsigned long long& iters,
                                           unsigned long long& exps) {
-    constexpr int STRIDE = b_stride_of(MW);
+    constexpr int STRIDE = lane_stride(MW);
     constexpr int SLOT = MW + 1;                    // saved level: R words + p
     const int lane = __lane_id();
     if (fresh) extract_rows<1, false>(s, P.row_ptr, P.col, lane, S, B, STRIDE);
@@ -136,8 +168,10 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
             const int i = b0 + lane;
             int c = 0;
             if (i < s) {
+                unsigned int row[MW];
+                load_row<MW>(B + i * STRIDE, row);
 #pragma unroll
-                for (int t = 0; t < MW; t++) c += __popc(B[i * STRIDE + t]);
+                for (int t = 0; t < MW; t++) c += __popc(row[t]);
             }
             int inc = c;
 #pragma unroll
@@ -245,19 +279,23 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                             if (!got && r < c) { j = 32 * w + select_bit(x, r); got = true; }
                             if (!got) r -= c;
                         }
-                        unsigned int c2 = 0;
+                        unsigned int c2 = 0, ri[MW], rj[MW];
+                        load_row<MW>(B + i * STRIDE, ri);
+                        load_row<MW>(B + j * STRIDE, rj);
 #pragma unroll
                         for (int w = 0; w < MW; w++) {
-                            R[w] = B[i * STRIDE + w] & B[j * STRIDE + w];
+                            R[w] = ri[w] & rj[w];
                             c2 += __popc(R[w]);
                         }
                         p = p0 + 1;
                         if (STATS) { nodes += 1; wsum += W; }
-                        if (p + 1 == k || p + 2 == k) {
+                        if (p + 1 == k || p + 2 == k || static_cast<int>(c2) < k - p) {
+                            // leaf levels counted at once; a set smaller than the
+                            // k - p vertices still missing holds no k-clique
                             if (p + 1 == k) {
                                 acc += c2;
-                            } else {
-                                acc += leaf_edges<MW, STRIDE>(R, B);
+                            } else if (p + 2 == k) {
+                                if (c2 >= 2) acc += leaf_edges<MW>(R, B);
                                 if (STATS) { nodes += c2; wsum += W * c2; }
                             }
 #pragma unroll
@@ -265,17 +303,17 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                         }
                     } else {
                         unsigned int c2 = 0;
+                        load_row<MW>(B + t * STRIDE, R);
 #pragma unroll
-                        for (int w = 0; w < MW; w++) {
-                            R[w] = B[t * STRIDE + w];
-                            c2 += __popc(R[w]);
-                        }
+                        for (int w = 0; w < MW; w++) c2 += __popc(R[w]);
                         p = p0;
-                        if (p + 1 == k || p + 2 == k) {
+                        if (p + 1 == k || p + 2 == k || static_cast<int>(c2) < k - p) {
+                            // leaf levels counted at once; a set smaller than the
+                            // k - p vertices still missing holds no k-clique
                             if (p + 1 == k) {
                                 acc += c2;
-                            } else {
-                                acc += leaf_edges<MW, STRIDE>(R, B);
+                            } else if (p + 2 == k) {
+                                if (c2 >= 2) acc += leaf_edges<MW>(R, B);
                                 if (STATS) { nodes += c2; wsum += W * c2; }
                             }
 #pragma unroll
@@ -381,10 +419,17 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
         busy = busy || depth > sbase;
         if (__ballot(busy || !out) == 0ull) break;
         if (busy) {
-            bool has = false;
+            int cnt = 0;
 #pragma unroll
-            for (int t = 0; t < MW; t++) has |= R[t] != 0u;
-            if (has) {
+            for (int t = 0; t < MW; t++) cnt += __popc(R[t]);
+            // a level with fewer candidates than the k - p vertices still missing
+            // holds no k-clique: drop it
+            if (cnt != 0 && cnt < k - p) {
+#pragma unroll
+                for (int t = 0; t < MW; t++) R[t] = 0u;
+                cnt = 0;
+            }
+            if (cnt != 0) {
                 if (STATS) exps += 1;
                 // expand the lowest candidate v
                 int v = 0;
@@ -398,27 +443,29 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                     }
                 }
                 unsigned int Y[MW];
-                unsigned int c = 0;
-                bool yany = false;
+                if constexpr (STRIDE % 4 == 0) {
+                    load_row<MW>(B + v * STRIDE, Y);
 #pragma unroll
-                for (int t = 0; t < MW; t++) {
-                    Y[t] = R[t] ? (R[t] & B[v * STRIDE + t]) : 0u;
-                    c += __popc(Y[t]);
-                    yany |= Y[t] != 0u;
+                    for (int t = 0; t < MW; t++) Y[t] &= R[t];
+                } else {
+#pragma unroll
+                    for (int t = 0; t < MW; t++) Y[t] = R[t] ? (R[t] & B[v * STRIDE + t]) : 0u;
                 }
+                int c = 0;
+#pragma unroll
+                for (int t = 0; t < MW; t++) c += __popc(Y[t]);
                 if (STATS) { nodes += 1; wsum += W; }
                 if (p + 2 == k) {
-                    acc += c;
+                    acc += static_cast<unsigned int>(c);
                 } else if (p + 3 == k) {
                     // Y holds the (k-1)-th vertex candidates: count the last
                     // level under it at once instead of descending
-                    if (yany) acc += leaf_edges<MW, STRIDE>(Y, B);
+                    if (c >= 2) acc += leaf_edges<MW>(Y, B);
                     if (STATS) { nodes += c; wsum += W * c; }
-                } else if (yany) {
-                    bool rany = false;
-#pragma unroll
-                    for (int t = 0; t < MW; t++) rany |= R[t] != 0u;
-                    if (rany) {
+                } else if (c >= k - p - 1) {
+                    // descend into Y; save the rest of this level only if it can
+                    // still complete a k-clique
+                    if (cnt - 1 >= k - p) {
                         unsigned int* f = stk + depth * SLOT * 64 + lane;
 #pragma unroll
                         for (int t = 0; t < MW; t++) f[t * 64] = R[t];
@@ -480,9 +527,9 @@ __device__ __forceinline__ void run_root(const LaneParams& P, const int* roots, 
 // tasks + helping (deep trees on wide roots); STATS: count expanded nodes.
 template <int MAXW, bool EC, bool PAIR, bool STATS>
 __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
-    constexpr int STRIDE = b_stride_of(MAXW);
+    constexpr int STRIDE = lane_stride(MAXW);
     constexpr int SLOT = MAXW + 1;                  // saved level: R words + p
-    extern __shared__ unsigned int lds[];
+    extern __shared__ __align__(16) unsigned int lds[];
     const int lane = threadIdx.x & 63;
     const int s_cap = P.s_cap;
     unsigned int* base = lds;
@@ -694,7 +741,7 @@ int launch_lane_t(const LaneParams& base, bool stats, int* grid_out, hipStream_t
     constexpr int SLOT = MAXW + 1;
     LaneParams P = base;
     P.s_cap = 32 * MAXW;
-    const int words = 16 + P.s_cap + P.s_cap * b_stride_of(MAXW) + (PAIR ? P.s_cap + 1 : 0) + 64 * SLOT +
+    const int words = 16 + P.s_cap + P.s_cap * lane_stride(MAXW) + (PAIR ? P.s_cap + 1 : 0) + 64 * SLOT +
                       P.levels * SLOT * 64;
     const size_t lds_bytes = static_cast<size_t>(words) * sizeof(unsigned int);
     (void)SLOT;
