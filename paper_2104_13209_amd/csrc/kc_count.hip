@@ -463,7 +463,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
     unsigned long long init[kAccWords] = {};
     init[0] = preload;
-    for (int j = 0; j < kWidthLists; j++) init[6 + 3 * kWidthLists + 3 * j + 1] = ~0ull;   // min start
+    for (int j = 0; j < kWidthLists; j++) init[6 + 4 * kWidthLists + 3 * j + 1] = ~0ull;   // min start of each list's timing
     KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
     if (pivot_all >= 0) {
         KC_CHECK(hipMemsetAsync(w.counts, 0, 2 * sizeof(unsigned long long) * (w.binom_n + 1), s));
@@ -522,6 +522,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         // deep trees: the widest list runs on a side stream beside the others, so
         // that the tail of its few large roots overlaps their work
         SideGuard side;
+        LaneLaunch side_launch;
         if (deep && top >= 1) {
             st = side_acquire(&side.s);
             if (st != KC_OK) return st;
@@ -560,11 +561,20 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.flags = w.ctl + CC_FLAGS;
             if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst], ls));
             L.grid_out = &lane_grid[lst];
+            if (on_side) side_launch = L;
             st = lane_launch(L, ls);
             if (st != KC_OK) return st;
             if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst + 1], ls));
         }
         if (side.held) {
+            // once the other lists are done, the rest of the device joins the
+            // widest list's tail: helpers take pair tasks and queued subtrees
+            LaneLaunch H = side_launch;
+            H.helper = true;
+            H.grid_out = nullptr;
+            H.timing_ptr = w.acc + 6 + 7 * kWidthLists;   // not part of the list's busy fraction
+            st = lane_launch(H, s);
+            if (st != KC_OK) return st;
             KC_CHECK(hipEventRecord(side.s.join, side.s.stream));
             KC_CHECK(hipStreamWaitEvent(s, side.s.join, 0));
         }

@@ -12,7 +12,7 @@ constexpr int kWidthLists = 6;         // root lists by bitset words per row: 1,
 constexpr int kQueueCap = 16384;        // lane walk: ring slots for subtrees handed between wavefronts (power of 2)
 constexpr int kItemWords = 36;          // queue item: root slot, path length, 2 spare, 32 words of R
 constexpr int kQueueCtlWords = 8;       // per width list: head, tail, pending, rooting, hungry
-constexpr int kAccWords = 6 + 7 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, expansions, busy, start, end
+constexpr int kAccWords = 9 + 7 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, expansions, busy, start, end
 
 enum CountCtl {
     CC_LIGHT_N = 0,      // light root count
@@ -144,6 +144,7 @@ struct LaneLaunch {
     int* task_tot;
     int* active;
     bool steal = false;   // hand subtrees to idle wavefronts through a global queue (pair mode)
+    bool helper = false;  // join a running launch of this list: help and take queued subtrees only
     int* qctl = nullptr;  // this list's queue control words (zero at launch)
     int* qready = nullptr;  // this list's ring slot sequence words (zero at launch)
     unsigned int* qitems = nullptr;

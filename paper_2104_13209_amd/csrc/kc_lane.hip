@@ -58,6 +58,7 @@ struct LaneParams {
     unsigned long long* gacc;       // batched: per-graph {lo, hi}; null otherwise
     const int* __restrict__ gid;    // batched: graph of each DAG vertex
     bool steal;                     // pair mode: subtree queue between wavefronts
+    bool helper;                    // joins a running launch: no roots of its own, no waiter cap
     int* qctl;                      // queue control words (zero at launch)
     int* qready;                    // per ring slot (zero at launch): g*cap free for the producer of
                                     // generation g, g*cap + 1 written, (g+1)*cap read
@@ -561,7 +562,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
     unsigned long long acc = 0, nodes = 0, wsum = 0, iters = 0, exps = 0, idle = 0;
     const unsigned long long t_begin = STATS ? __builtin_amdgcn_s_memrealtime() : 0ull;
     if (steal && lane == 0) atomicAdd(&q[Q_ROOTING], 1);    // in the root phase
-    bool helping = false;
+    bool helping = steal && P.helper;               // helpers own no roots (and no registry entry)
     int rq = 0, rq_end = 0;                         // claimed, unprocessed root range
     constexpr int RC = PAIR ? 1 : kRootChunk;
 
@@ -623,7 +624,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
         // compute unit slots for launches that run beside this one.  A waiter
         // leaves only at the end, so handed-over subtrees always find one.
         int stay = 1;
-        if (lane == 0 && atomicAdd(&q[Q_HUNGRY], 1) >= kMaxWaiters) {
+        if (lane == 0 && atomicAdd(&q[Q_HUNGRY], 1) >= kMaxWaiters && !P.helper) {
             atomicAdd(&q[Q_HUNGRY], -1);
             stay = 0;
         }
@@ -789,6 +790,7 @@ int lane_launch(const LaneLaunch& L, hipStream_t s) {
     P.gacc = L.gacc;
     P.gid = L.gid;
     P.steal = L.pair && L.steal;
+    P.helper = L.helper && P.steal;
     P.qctl = L.qctl;
     P.qready = L.qready;
     P.qitems = L.qitems;
