@@ -140,6 +140,85 @@ __device__ __forceinline__ int root_size(int r, int need, const int* __restrict_
     return c;
 }
 
+// Exact |S| of every edge root (u, v), one wavefront per source vertex u: the
+// row N+(u) is staged in LDS, then four 16-lane groups take the row's edges in
+// turn; a group reads N+(v) coalesced and binary-searches each entry in the tail
+// of N+(u) past v.  lst_of[r] gets the root's width list (-1 when |S| < need);
+// the list sizes go to ctl[CC_WN0 + j].  cap >= the longest DAG row.
+constexpr int kSizeWaves = 4;   // wavefronts per block
+__global__ void __launch_bounds__(64 * kSizeWaves) k_sizes_ec(int n, int need, const int* __restrict__ row_ptr,
+                                                             const int* __restrict__ col,
+                                                             const int* __restrict__ src, int* lst_of, int* ctl,
+                                                             int cap) {
+    extern __shared__ int su_all[];
+    const int lane = threadIdx.x & 63;
+    int* su = su_all + (threadIdx.x >> 6) * cap;
+    const int g = lane >> 4, gl = lane & 15;
+    const unsigned long long gmask = 0xFFFFull << (16 * g);
+    int cnt[kWidthLists];
+#pragma unroll
+    for (int q = 0; q < kWidthLists; q++) cnt[q] = 0;
+    const int nw = gridDim.x * kSizeWaves;
+    for (int u = blockIdx.x * kSizeWaves + static_cast<int>(threadIdx.x >> 6); u < n; u += nw) {
+        const int b = row_ptr[u], du = row_ptr[u + 1] - b;
+        if (du == 0) continue;
+        if (du > cap) {
+            // a row longer than the stated d_max: per-edge search in global memory
+            for (int i = lane; i < du; i += 64) {
+                const int size = root_size<true>(b + i, need, row_ptr, col, src);
+                const int lst = size >= need ? width_list(size) : -1;
+#pragma unroll
+                for (int q = 0; q < kWidthLists; q++) cnt[q] += lst == q;
+                lst_of[b + i] = lst;
+            }
+            continue;
+        }
+        for (int i = lane; i < du; i += 64) su[i] = col[b + i];
+        wave_sync_lds();
+        for (int j0 = 0; j0 < du; j0 += 4) {
+            const int j = j0 + g;
+            bool live = j < du;
+            int vb = 0, len = 0;
+            if (live) {
+                const int v = su[j];
+                vb = row_ptr[v];
+                len = row_ptr[v + 1] - vb;
+                if (du - j - 1 < need || len < need) live = false;
+            }
+            if (!live) len = 0;
+            // rounds of 16 entries of N+(v) per group, as many as the longest row
+            const int rounds = wave_max(len);
+            int hits = 0;
+            for (int t0 = 0; t0 < rounds; t0 += 16) {
+                const int t = t0 + gl;
+                bool hit = false;
+                if (t < len) {
+                    const int x = col[vb + t];
+                    int lo = j + 1, hi = du;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (su[mid] < x) lo = mid + 1; else hi = mid;
+                    }
+                    hit = lo < du && su[lo] == x;
+                }
+                hits += __popcll(__ballot(hit) & gmask);
+            }
+            if (gl == 0 && j < du) {
+                const int lst = live && hits >= need ? width_list(hits) : -1;
+#pragma unroll
+                for (int q = 0; q < kWidthLists; q++) cnt[q] += lst == q;
+                lst_of[b + j] = lst;
+            }
+        }
+        wave_sync_lds();
+    }
+#pragma unroll
+    for (int q = 0; q < kWidthLists; q++) {
+        const int tot = wave_sum(cnt[q]);
+        if (lane == 0 && tot) atomicAdd(&ctl[CC_WN0 + q], tot);
+    }
+}
+
 template <bool EC, bool FILL>
 __global__ void __launch_bounds__(kBlock) k_classify_w(int nroots_total, int need, const int* __restrict__ row_ptr,
                                                       const int* __restrict__ col, const int* __restrict__ src,
@@ -492,10 +571,16 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             KC_CHECK(hipMemsetAsync(w.qctl, 0, sizeof(int) * kQueueCtlWords * kWidthLists, s));
             KC_CHECK(hipMemsetAsync(w.qready, 0, sizeof(int) * kQueueCap * kWidthLists, s));
         }
-        if (ec)
-            k_classify_w<true, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl, w.heavy);
-        else
+        if (ec) {
+            const int cap = d->d_max > 1 ? d->d_max : 1;
+            int sblocks = div_up(d->n, kSizeWaves);
+            if (sblocks > device_cus() * 8) sblocks = device_cus() * 8;
+            if (sblocks < 1) sblocks = 1;
+            k_sizes_ec<<<sblocks, 64 * kSizeWaves, kSizeWaves * cap * sizeof(int), s>>>(
+                d->n, need, d->row_ptr, d->col, d->src, w.heavy, w.ctl, cap);
+        } else {
             k_classify_w<false, false><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.ctl, w.heavy);
+        }
     } else if (ec) {
         k_classify<true><<<cblocks, kBlock, 0, s>>>(nroots, need, d->row_ptr, d->col, d->src, w.light, w.heavy, w.ctl);
     } else {
