@@ -402,6 +402,8 @@ def main():
         "wavefronts": int(sp.waves_width[dom_j]),
         "width_list_busy_fraction": [round(float(sp.busy_width[j]), 4) for j in range(6)],
         "width_list_nodes": [int(sp.nodes_width[j]) for j in range(6)],
+        "width_list_wave_iterations": [int(sp.iters_width[j]) for j in range(6)],
+        "width_list_expansions": [int(sp.expand_width[j]) for j in range(6)],
     }
 
     batched = None
