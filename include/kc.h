@@ -117,17 +117,23 @@ typedef struct kc_profile {
     int32_t items_width[6];    /* subtrees handed between wavefronts (pair mode) */
 } kc_profile;
 
+/* Flags of kc_opts (deep non-pivot counts on the default lane walk):
+ * KC_OPT_NO_HANDOFF      wavefronts never hand subtrees to idle wavefronts;
+ * KC_OPT_SINGLE_STREAM   every launch stays on the caller's stream (no side
+ *                        stream for the widest root list, no helper launch):
+ *                        for callers that already run many counts at once. */
+enum { KC_OPT_NO_HANDOFF = 1, KC_OPT_SINGLE_STREAM = 2 };
+
 /* Tuning options; NULL means defaults.  scheme: KC_SCHEME_*; width: lanes per
  * sub-wavefront group (1, 2, 4, 8, 16, 32 or 64; 0 = auto) (Sec. 3.5).
- * collect_stats and profile: see kc_profile.
+ * collect_stats and profile: see kc_profile.  flags: KC_OPT_* bits.
  * test_preload: added to the internal accumulator before counting; it exists
  * only so that tests can drive the 64-bit overflow path, and is 0 in normal use. */
 typedef struct kc_opts {
     int32_t scheme;
     int32_t width;
     int32_t collect_stats;
-    int32_t no_handoff;        /* 1: wavefronts never hand subtrees to idle ones
-                                  (deep non-pivot counts; for measurement)     */
+    int32_t flags;
     uint64_t test_preload;
     kc_profile* profile;
 } kc_opts;

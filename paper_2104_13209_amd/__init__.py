@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_PKG, "libkc.so")
 
 ORDER_DEGREE, ORDER_DEGENERACY = 0, 1
 SCHEME_AUTO, SCHEME_VC, SCHEME_EC = 0, 1, 2
+OPT_NO_HANDOFF, OPT_SINGLE_STREAM = 1, 2
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ECANCELED, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MAX_DMAX = 1024
 
@@ -65,7 +66,7 @@ class Profile(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("width", ctypes.c_int32),
-                ("collect_stats", ctypes.c_int32), ("no_handoff", ctypes.c_int32),
+                ("collect_stats", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("test_preload", ctypes.c_uint64), ("profile", ctypes.POINTER(Profile))]
 
 
@@ -189,8 +190,9 @@ def orient(g: Csr, order: int = ORDER_DEGREE, validate: bool = True, ws: torch.T
 
 
 def _opts(scheme: int, width: int, test_preload: int, profile: Profile | None = None,
-          collect_stats: bool = False, handoff: bool = True) -> _Opts:
-    o = _Opts(scheme, width, int(bool(collect_stats)), int(not handoff), test_preload, None)
+          collect_stats: bool = False, handoff: bool = True, single_stream: bool = False) -> _Opts:
+    flags = (0 if handoff else OPT_NO_HANDOFF) | (OPT_SINGLE_STREAM if single_stream else 0)
+    o = _Opts(scheme, width, int(bool(collect_stats)), flags, test_preload, None)
     if profile is not None:
         o.profile = ctypes.pointer(profile)
     return o
@@ -204,11 +206,12 @@ def count_workspace_bytes(d: Dag, k: int, pivot: bool, scheme: int = 0, width: i
 
 def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
                  ws: torch.Tensor | None = None, test_preload: int = 0, stream=None,
-                 profile: Profile | None = None, collect_stats: bool = False, handoff: bool = True):
+                 profile: Profile | None = None, collect_stats: bool = False, handoff: bool = True,
+                 single_stream: bool = False):
     """(status, count) of kc_count without raising."""
     L = lib()
     cd = d._c()
-    o = _opts(scheme, width, test_preload, profile, collect_stats, handoff)
+    o = _opts(scheme, width, test_preload, profile, collect_stats, handoff, single_stream)
     need = int(L.kc_count_workspace(ctypes.byref(cd), k, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)
@@ -220,10 +223,12 @@ def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
 
 def count(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
           ws: torch.Tensor | None = None, stream=None, profile: Profile | None = None,
-          collect_stats: bool = False, handoff: bool = True) -> int:
+          collect_stats: bool = False, handoff: bool = True, single_stream: bool = False) -> int:
     """Number of k-cliques (kc_count); exact Python int.  handoff=False keeps
-    every subtree on the wavefront that found it (measurement)."""
-    st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream, profile, collect_stats, handoff)
+    every subtree on the wavefront that found it; single_stream=True keeps every
+    launch on `stream` (KC_OPT_* flags)."""
+    st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream, profile, collect_stats, handoff,
+                           single_stream)
     if st != OK:
         raise KcError(st, "kc_count")
     return val

@@ -608,7 +608,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         // that the tail of its few large roots overlaps their work
         SideGuard side;
         LaneLaunch side_launch;
-        if (deep && top >= 1) {
+        if (deep && top >= 1 && !(o && (o->flags & KC_OPT_SINGLE_STREAM))) {
             st = side_acquire(&side.s);
             if (st != KC_OK) return st;
             side.held = true;
@@ -639,7 +639,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.stats_ptr = w.acc + 6 + 2 * lst;
             L.iters_ptr = w.acc + 6 + 2 * kWidthLists + 2 * lst;
             L.timing_ptr = w.acc + 6 + 4 * kWidthLists + 3 * lst;
-            L.steal = L.pair && !(o && o->no_handoff);
+            L.steal = L.pair && !(o && (o->flags & KC_OPT_NO_HANDOFF));
             L.qctl = w.qctl + kQueueCtlWords * lst;
             L.qready = w.qready + static_cast<size_t>(kQueueCap) * lst;
             L.qitems = w.qitems + (on_side ? static_cast<size_t>(kQueueCap) * kItemWords : 0);

@@ -126,7 +126,10 @@ struct kc_server {
             }
             q->t_start = kc::now_s();
             const kc_dag* d = &dags[q->graph];
-            q->status = kc_count(d, q->k, q->pivot, &q->count, arena_mem + q->off, q->need, nullptr, s);
+            // concurrency comes from the other queries: keep each count on its worker's stream
+            kc_opts o{};
+            o.flags = KC_OPT_SINGLE_STREAM;
+            q->status = kc_count(d, q->k, q->pivot, &q->count, arena_mem + q->off, q->need, &o, s);
             q->t_done = kc::now_s();
             {
                 std::lock_guard<std::mutex> lk(mu);

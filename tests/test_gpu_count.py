@@ -67,6 +67,18 @@ def test_widths_agree(kc, cache, width):
             assert kc.count(d, k, scheme=scheme, width=width) == want[k], (width, scheme, k)
 
 
+@pytest.mark.parametrize("handoff,single_stream", [(True, False), (False, False), (True, True), (False, True)])
+def test_scheduling_options_agree(kc, cache, handoff, single_stream):
+    # deep counts on wide roots: subtree handoff between wavefronts, the widest
+    # list on a side stream with a helper launch, or all on one stream
+    g, d = get(cache, kc, "heavy_core", kc.ORDER_DEGENERACY)
+    want = oracle_counts(g, (7, 8, 9))
+    for scheme in (1, 2):
+        for k in (7, 8, 9):
+            got = kc.count(d, k, scheme=scheme, handoff=handoff, single_stream=single_stream)
+            assert got == want[k], (handoff, single_stream, scheme, k)
+
+
 def test_complete_graph_closed_form(kc):
     for n in (33, 64, 65, 100, 129, 200, 300, 520):
         g = synth.complete(n)
