@@ -397,7 +397,7 @@ def main():
                 "%d nodes with rows of at most %d words (the root's own word count each) = %d words in one "
                 "launch of %.3f ms (HIP events, mean of timed steps)"
                 % (sp.nodes_width[dom_j], 1 << dom_j, sp.words_width[dom_j], dom_ms),
-        "lane_utilisation": round(sp.expand_width[dom_j] / max(1, 64 * sp.iters_width[dom_j]), 4),
+        "lane_expansions_per_round": round(sp.expand_width[dom_j] / max(1, 64 * sp.iters_width[dom_j]), 4),
         "wavefront_busy_fraction": round(float(sp.busy_width[dom_j]), 4),
         "wavefronts": int(sp.waves_width[dom_j]),
         "width_list_busy_fraction": [round(float(sp.busy_width[j]), 4) for j in range(6)],

@@ -109,9 +109,9 @@ typedef struct kc_profile {
     int32_t roots_width[6];
     uint64_t nodes_width[6];
     uint64_t words_width[6];
-    uint64_t iters_width[6];   /* wavefront loop iterations                      */
-    uint64_t expand_width[6];  /* lane-iterations that expanded a node (lane
-                                  utilisation = expand / (64 x iterations))     */
+    uint64_t iters_width[6];   /* wavefront rounds (checks + up to 8 lane steps) */
+    uint64_t expand_width[6];  /* node expansions summed over lanes; expand /
+                                  (64 x rounds) = expansions per lane and round */
     int32_t waves_width[6];    /* wavefronts launched                           */
     float busy_width[6];       /* mean wavefront busy time / launch span         */
     int32_t items_width[6];    /* subtrees handed between wavefronts (pair mode) */

@@ -30,6 +30,7 @@ namespace {
 constexpr int kPairChunk = 64;    // pair tasks claimed per global atomic
 constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
 constexpr int kStealEvery = 128;  // loop iterations between looks at the subtree queue
+constexpr int kInner = 8;         // lane-local steps per wavefront-level round
 constexpr int kStealMax = 8;      // subtrees handed over per look
 constexpr int kMaxWaiters = 256;  // wavefronts that wait for handed-over subtrees; the rest leave
 // queue control words
@@ -419,7 +420,21 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
         for (int t = 0; t < MW; t++) busy |= R[t] != 0u;
         busy = busy || depth > sbase;
         if (__ballot(busy || !out) == 0ull) break;
-        if (busy) {
+        // up to kInner steps of lane-local work (pop a saved level, expand one
+        // node) between the wavefront-level checks above
+        for (int st = 0; st < kInner; st++) {
+            if (st > 0) {
+                bool e2 = true;
+#pragma unroll
+                for (int t = 0; t < MW; t++) e2 &= R[t] == 0u;
+                if (e2 && depth > sbase) {
+                    depth--;
+                    const unsigned int* f = stk + depth * SLOT * 64 + lane;
+#pragma unroll
+                    for (int t = 0; t < MW; t++) R[t] = f[t * 64];
+                    p = static_cast<int>(f[MW * 64]);
+                }
+            }
             int cnt = 0;
 #pragma unroll
             for (int t = 0; t < MW; t++) cnt += __popc(R[t]);
@@ -477,6 +492,12 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                     for (int t = 0; t < MW; t++) R[t] = Y[t];
                     p++;
                 }
+            }
+            if (st + 1 < kInner) {
+                bool more = depth > sbase;
+#pragma unroll
+                for (int t = 0; t < MW; t++) more |= R[t] != 0u;
+                if (__ballot(more) == 0ull) break;
             }
         }
     }
