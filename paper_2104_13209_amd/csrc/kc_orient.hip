@@ -37,6 +37,7 @@ enum Ctl {
     CTL_ZEROS = 6,     // zero count of the current radix pass
     CTL_SIZE0 = 8,     // peel frontier sizes, ring of 3 (8, 9, 10)
     CTL_MIN = 11,      // peel level minimum
+    CTL_HSIZE0 = 12,   // peel heavy-frontier sizes, ring of 3 (12, 13, 14)
     CTL_WORDS = 16
 };
 
@@ -99,28 +100,79 @@ __device__ __forceinline__ void append_wave(bool flag, int v, int* list, int* si
     if (flag) list[base + __popcll(m & lanemask_lt())] = v;
 }
 
-// One peeling round: the frontier's vertices get round r, and every live
-// neighbour loses one degree; a neighbour that drops to the level c joins the
-// next frontier.  Wavefront wave of nwaves takes frontier entries wave, wave +
-// nwaves, ...; its lanes split the vertex's row.
-__device__ __forceinline__ void peel_round(int r, int c, const int* cur, int fsize, int* nxt, int* nsize,
-                                           const int* __restrict__ row_ptr, const int* __restrict__ col, int* deg,
-                                           int* rnd, int wave, int nwaves, int lane) {
+// Frontier of one peeling round, split by row length: light vertices (rows of
+// at most kHeavyRow entries) are walked by one wavefront each, the rows of heavy
+// vertices are cut into 64-entry chunks that all wavefronts share.
+constexpr int kHeavyRow = 128;
+struct Frontier {
+    int* light;
+    int* heavy;
+    int* nlight;
+    int* nheavy;
+};
+
+// Appends flagged vertices to the light or heavy list by row length.
+__device__ __forceinline__ void append_split(bool flag, int v, const int* __restrict__ row_ptr, const Frontier& f,
+                                             int lane) {
+    bool heavy = false;
+    if (flag) heavy = row_ptr[v + 1] - row_ptr[v] > kHeavyRow;
+    append_wave(flag && !heavy, v, f.light, f.nlight, lane);
+    append_wave(flag && heavy, v, f.heavy, f.nheavy, lane);
+}
+
+// One entry of the row being peeled: a live neighbour loses one degree and joins
+// the next frontier when it drops to the level c.  A stale read of a vertex
+// removed earlier only decrements a dead degree, which never equals c + 1.
+__device__ __forceinline__ void peel_entry(int j, int e, int c, const int* __restrict__ row_ptr,
+                                           const int* __restrict__ col, int* deg, const int* rnd,
+                                           const Frontier& nx, int lane) {
+    bool hit = false;
+    int w = 0;
+    if (j < e) {
+        w = col[j];
+        if (ld_acquire(&rnd[w]) < 0) hit = atomicSub(&deg[w], 1) == c + 1;
+    }
+    append_split(hit, w, row_ptr, nx, lane);
+}
+
+// One peeling round: the frontier's vertices get round r and their live
+// neighbours lose one degree each.  Light vertices: wavefront `wave` of nwaves
+// takes entries wave, wave + nwaves, ...  Heavy vertices, 64 at a time: every
+// wavefront reads their row lengths, numbers the 64-entry chunks of all their
+// rows, and takes chunks wave, wave + nwaves, ...
+__device__ __forceinline__ void peel_round(int r, int c, const int* cur, int fsize, const int* hcur, int hsize,
+                                           const Frontier& nx, const int* __restrict__ row_ptr,
+                                           const int* __restrict__ col, int* deg, int* rnd, int wave, int nwaves,
+                                           int lane) {
     for (int fi = wave; fi < fsize; fi += nwaves) {
         const int v = ld_acquire(&cur[fi]);
         if (lane == 0) rnd[v] = r;
         const int b = row_ptr[v], e = row_ptr[v + 1];
-        for (int j0 = b; j0 < e; j0 += 64) {
-            const int j = j0 + lane;
-            bool hit = false;
-            int w = 0;
-            if (j < e) {
-                w = col[j];
-                // a stale read of a vertex removed earlier only decrements a dead
-                // degree, which never equals c + 1 any more
-                if (ld_acquire(&rnd[w]) < 0) hit = atomicSub(&deg[w], 1) == c + 1;
-            }
-            append_wave(hit, w, nxt, nsize, lane);
+        for (int j0 = b; j0 < e; j0 += 64) peel_entry(j0 + lane, e, c, row_ptr, col, deg, rnd, nx, lane);
+    }
+    for (int h0 = 0; h0 < hsize; h0 += 64) {
+        const int hi = h0 + lane;
+        int v = 0, b = 0, e = 0, nch = 0;
+        if (hi < hsize) {
+            v = ld_acquire(&hcur[hi]);
+            b = row_ptr[v];
+            e = row_ptr[v + 1];
+            nch = (e - b + 63) >> 6;
+            if (wave == 0) rnd[v] = r;
+        }
+        int incl = nch;                          // inclusive prefix of chunk counts
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        const int excl = incl - nch;
+        const int total = __shfl(incl, 63);
+        for (int q = wave; q < total; q += nwaves) {
+            // owner: the last lane whose exclusive prefix is <= q
+            const int owner = __popcll(__ballot(hi < hsize && excl <= q)) - 1;
+            const int ob = __shfl(b, owner), oe = __shfl(e, owner), ox = __shfl(excl, owner);
+            peel_entry(ob + (q - ox) * 64 + lane, oe, c, row_ptr, col, deg, rnd, nx, lane);
         }
     }
 }
@@ -143,7 +195,7 @@ __device__ __forceinline__ void peel_round(int r, int c, const int* cur, int fsi
 // wavefront.
 __global__ void __launch_bounds__(kBlock) k_peel(int n, const int* __restrict__ row_ptr,
                                                 const int* __restrict__ col, int* deg, int* rnd,
-                                                int* fr0, int* fr1, int* val, int* ctl) {
+                                                int* fr0, int* fr1, int* hf0, int* hf1, int* val, int* ctl) {
     cg::grid_group grid = cg::this_grid();
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nth = gridDim.x * blockDim.x;
@@ -158,23 +210,25 @@ __global__ void __launch_bounds__(kBlock) k_peel(int n, const int* __restrict__ 
     }
     if (tid == 0) {
         ctl[CTL_SIZE0] = ctl[CTL_SIZE0 + 1] = ctl[CTL_SIZE0 + 2] = 0;
+        ctl[CTL_HSIZE0] = ctl[CTL_HSIZE0 + 1] = ctl[CTL_HSIZE0 + 2] = 0;
         ctl[CTL_MIN] = INT_MAX;
     }
     grid.sync();
 
     int removed = 0, r = 0, c = -1, degen = 0;
     while (removed < n) {
-        int* cur = (r & 1) ? fr1 : fr0;
-        int* nxt = (r & 1) ? fr0 : fr1;
-        int* csize = &ctl[CTL_SIZE0 + r % 3];
-        int* nsize = &ctl[CTL_SIZE0 + (r + 1) % 3];
-        const int fsize = ld_acquire(csize);
-        if (fsize == 0) {
+        const int* cur = (r & 1) ? fr1 : fr0;
+        const int* hcur = (r & 1) ? hf1 : hf0;
+        const Frontier nx{(r & 1) ? fr0 : fr1, (r & 1) ? hf0 : hf1, &ctl[CTL_SIZE0 + (r + 1) % 3],
+                          &ctl[CTL_HSIZE0 + (r + 1) % 3]};
+        const int fsize = ld_acquire(&ctl[CTL_SIZE0 + r % 3]);
+        const int hsize = ld_acquire(&ctl[CTL_HSIZE0 + r % 3]);
+        if (fsize + hsize == 0) {
             // Level change, as an empty round r: the next frontier is collected
-            // into nxt (no block reads nsize or nxt while others may still be
+            // into the next lists (no block reads those while others may still be
             // reading csize above), then round r + 1 peels it.  One pass takes
             // the live vertices of degree <= c + 1 and the minimum live degree.
-            if (tid == 0) ctl[CTL_SIZE0 + (r + 2) % 3] = 0;
+            if (tid == 0) ctl[CTL_SIZE0 + (r + 2) % 3] = ctl[CTL_HSIZE0 + (r + 2) % 3] = 0;
             int mn = INT_MAX;
             for (int b0 = tid - lane; b0 < n; b0 += nth) {
                 const int v = b0 + lane;
@@ -184,19 +238,19 @@ __global__ void __launch_bounds__(kBlock) k_peel(int n, const int* __restrict__ 
                     mn = d < mn ? d : mn;
                     in = d <= c + 1;
                 }
-                append_wave(in, v, nxt, nsize, lane);
+                append_split(in, v, row_ptr, nx, lane);
             }
             mn = wave_min(mn);
             if (lane == 0 && mn != INT_MAX) atomicMin(&ctl[CTL_MIN], mn);
             grid.sync();
-            if (ld_acquire(nsize) > 0) {
+            if (ld_acquire(nx.nlight) + ld_acquire(nx.nheavy) > 0) {
                 c = c + 1;          // the minimum live degree is c + 1
             } else {
                 c = ld_acquire(&ctl[CTL_MIN]);
                 for (int b0 = tid - lane; b0 < n; b0 += nth) {
                     const int v = b0 + lane;
                     const bool in = v < n && ld_acquire(&rnd[v]) < 0 && ld_acquire(&deg[v]) <= c;
-                    append_wave(in, v, nxt, nsize, lane);
+                    append_split(in, v, row_ptr, nx, lane);
                 }
                 grid.sync();
             }
@@ -205,9 +259,9 @@ __global__ void __launch_bounds__(kBlock) k_peel(int n, const int* __restrict__ 
             r++;
             continue;
         }
-        if (tid == 0) ctl[CTL_SIZE0 + (r + 2) % 3] = 0;
-        peel_round(r, c, cur, fsize, nxt, nsize, row_ptr, col, deg, rnd, wave, nwaves, lane);
-        removed += fsize;
+        if (tid == 0) ctl[CTL_SIZE0 + (r + 2) % 3] = ctl[CTL_HSIZE0 + (r + 2) % 3] = 0;
+        peel_round(r, c, cur, fsize, hcur, hsize, nx, row_ptr, col, deg, rnd, wave, nwaves, lane);
+        removed += fsize + hsize;
         r++;
         grid.sync();
     }
@@ -437,7 +491,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_long_rows(int n, const int* __r
 }
 
 struct OrientWs {
-    int *ctl, *key_a, *val_a, *key_b, *val_b, *rank, *outdeg, *tiles, *rnd, *fr0, *fr1, *tmp;
+    int *ctl, *key_a, *val_a, *key_b, *val_b, *rank, *outdeg, *tiles, *rnd, *fr0, *fr1, *hf0, *hf1, *tmp;
 };
 
 OrientWs carve(void* ws, int n, int nnz, size_t* bytes) {
@@ -457,6 +511,8 @@ OrientWs carve(void* ws, int n, int nnz, size_t* bytes) {
     w.rnd = c.take<int>(nn);
     w.fr0 = c.take<int>(nn);
     w.fr1 = c.take<int>(nn);
+    w.hf0 = c.take<int>(nn);
+    w.hf1 = c.take<int>(nn);
     w.tmp = c.take<int>(m);
     *bytes = c.bytes();
     return w;
@@ -599,7 +655,7 @@ extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out,
         const int* rp = g->row_ptr;
         const int* cl = g->col;
         int* deg = w.key_b;   // scratch until the sort
-        void* args[] = {&n_, &rp, &cl, &deg, &w.rnd, &w.fr0, &w.fr1, &w.val_a, &w.ctl};
+        void* args[] = {&n_, &rp, &cl, &deg, &w.rnd, &w.fr0, &w.fr1, &w.hf0, &w.hf1, &w.val_a, &w.ctl};
         KC_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<void*>(k_peel), dim3(blocks), dim3(kBlock),
                                             args, 0, s));
         KC_CHECK(hipMemcpyAsync(w.key_a, w.rnd, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
