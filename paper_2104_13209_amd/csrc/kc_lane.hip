@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kPairChunk = 64;    // pair tasks claimed per global atomic
 constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
-constexpr int kStealEvery = 128;  // loop iterations between looks at the subtree queue
+constexpr int kStealEvery = 16;   // wavefront rounds (up to 8 lane steps each) between looks at the subtree queue
 constexpr int kInner = 8;         // lane-local steps per wavefront-level round
 constexpr int kStealMax = 8;      // subtrees handed over per look
 constexpr int kMaxWaiters = 256;  // wavefronts that wait for handed-over subtrees; the rest leave
@@ -124,6 +124,32 @@ __device__ __forceinline__ unsigned int leaf_edges(const unsigned int (&Y)[MW], 
         }
     }
     return c;
+}
+
+// Lowest set bit of R (R not empty): returns its index and clears it.  Words are
+// taken in 64-bit pairs, which halves the select chain.
+template <int MW>
+__device__ __forceinline__ int pop_lowest(unsigned int (&R)[MW]) {
+    int v = 0;
+    bool got = false;
+#pragma unroll
+    for (int t = 0; t < MW; t += 2) {
+        if (t + 1 < MW) {
+            unsigned long long x = (static_cast<unsigned long long>(R[t + 1]) << 32) | R[t];
+            if (!got && x != 0ull) {
+                v = 32 * t + __ffsll(x) - 1;
+                x &= x - 1ull;
+                R[t] = static_cast<unsigned int>(x);
+                R[t + 1] = static_cast<unsigned int>(x >> 32);
+                got = true;
+            }
+        } else if (!got && R[t] != 0u) {
+            v = 32 * t + __ffs(R[t]) - 1;
+            R[t] &= R[t] - 1u;
+            got = true;
+        }
+    }
+    return v;
 }
 
 // Words [0, MW) of a bitset row at stride lane_stride(MW): 32-bit reads for odd
@@ -448,25 +474,11 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
             if (cnt != 0) {
                 if (STATS) exps += 1;
                 // expand the lowest candidate v
-                int v = 0;
-                bool got = false;
-#pragma unroll
-                for (int t = 0; t < MW; t++) {
-                    if (!got && R[t] != 0u) {
-                        v = 32 * t + __ffs(R[t]) - 1;
-                        R[t] &= R[t] - 1u;
-                        got = true;
-                    }
-                }
+                const int v = pop_lowest<MW>(R);
                 unsigned int Y[MW];
-                if constexpr (STRIDE % 4 == 0) {
-                    load_row<MW>(B + v * STRIDE, Y);
+                load_row<MW>(B + v * STRIDE, Y);
 #pragma unroll
-                    for (int t = 0; t < MW; t++) Y[t] &= R[t];
-                } else {
-#pragma unroll
-                    for (int t = 0; t < MW; t++) Y[t] = R[t] ? (R[t] & B[v * STRIDE + t]) : 0u;
-                }
+                for (int t = 0; t < MW; t++) Y[t] &= R[t];
                 int c = 0;
 #pragma unroll
                 for (int t = 0; t < MW; t++) c += __popc(Y[t]);
