@@ -159,6 +159,46 @@ def bench_batched(kc, ngraphs, k, reps):
     }
 
 
+def bench_densecore(kc, reps):
+    """Pivot count-all (every k, 128-bit) on the dense-core workload, with the
+    counts compared to the oracle's stored in tests/golden/."""
+    import torch
+    import synth
+    t0 = time.perf_counter()
+    g = synth.config_densecore()
+    log("dense core: n=%d m=%d (%.1f s)" % (g.n, g.m, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    d = kc.orient(kc.to_device(g, dev), kc.ORDER_DEGENERACY)
+    out = {"workload": "Chung-Lu background n=%d, mean degree 40, exponent 2.1, w_max 1000, seed 3, plus 50 "
+                       "communities of U[60, 80] vertices at density 0.9; degeneracy order, pivoting, all k" % g.n,
+           "n": g.n, "m": g.m, "d_max": d.d_max, "degeneracy": d.degeneracy}
+    fixture = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "densecore_count_all.txt")
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) == 3 and parts[0] == "c":
+                    fixture[int(parts[1])] = int(parts[2])
+    for name, scheme in (("vc", kc.SCHEME_VC), ("ec", kc.SCHEME_EC)):
+        ws = torch.empty(kc.count_workspace_bytes(d, 0, True, scheme), dtype=torch.uint8, device=dev)
+        got, omega = kc.count_all(d, pivot=True, scheme=scheme, ws=ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            got, omega = kc.count_all(d, pivot=True, scheme=scheme, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"count_all_ms": round(ms, 3), "edges_per_s": g.m / (ms / 1e3), "omega": omega,
+                     "matches_oracle_counts": (got[:omega + 1] == [fixture.get(k) for k in range(omega + 1)])
+                     if fixture else None}
+        log("dense core %s: count-all %.1f ms, omega %d" % (name, ms, omega))
+    out["total_cliques"] = str(sum(got[1:]))
+    return out
+
+
 def served_pool(ngraphs, nmin, nmax, seed=5):
     """Pool of graphs for serving: shapes uniform over {power-law Chung-Lu
     (gamma 2.1, mean 32, w_max = sqrt(sum w)), dense core (Chung-Lu background +
@@ -275,6 +315,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-util", type=float, default=0.7)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--dense-reps", type=int, default=2)
+    ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -412,6 +454,11 @@ def main():
         batched = bench_batched(kc, args.batch_graphs, args.batch_k, args.batch_reps)
         log("batched: %.0f graphs/s vs plain %.0f graphs/s" % (batched["graphs_per_s"], batched["plain_graphs_per_s"]))
 
+    dense = None
+    if not args.no_dense:
+        log("dense-core form ...")
+        dense = bench_densecore(kc, args.dense_reps)
+
     served = None
     if not args.no_serve:
         log("served form ...")
@@ -450,6 +497,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "dense_core": dense,
         "served": served,
     }
     print(json.dumps(res), flush=True)

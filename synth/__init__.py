@@ -199,10 +199,10 @@ def communities_pairs(n: int, nc: int, smin: int, smax: int, p: float, seed: int
 
 
 def dense_core(n: int, mean: float, gamma: float, nc: int, smin: int, smax: int, p: float,
-               seed: int) -> Graph:
-    """Chung-Lu background (w_max = sqrt(sum w), so no saturated core) plus `nc`
-    planted communities with intra-density p."""
-    wmax = math.sqrt(n * mean)
+               seed: int, wmax: float = 0.0) -> Graph:
+    """Chung-Lu background (w_max = sqrt(sum w) unless given, so no saturated
+    core) plus `nc` planted communities with intra-density p."""
+    wmax = wmax if wmax > 0 else math.sqrt(n * mean)
     w = powerlaw_weights(n, gamma, mean, wmax, seed)
     bg = chung_lu_pairs(w, seed)
     cm, _ = communities_pairs(n, nc, smin, smax, p, seed + 1)
@@ -333,6 +333,17 @@ def batch(ngraphs: int, seed: int = 4, nmin: int = 50, nmax: int = 5000, dmin: f
 def config_small(seed: int = 1) -> Graph:
     """Erdos-Renyi G(2000, 0.01): the small plain-method workload."""
     return erdos_renyi(2000, 0.01, seed)
+
+
+def config_densecore(seed: int = 3, n: int = 500_000, mean: float = 40.0, nc: int = 50, smin: int = 60,
+                     smax: int = 80, p: float = 0.9, gamma: float = 2.1, wmax: float = 1000.0) -> Graph:
+    """Dense-core workload: Chung-Lu background (n = 500k, mean degree 40, exponent
+    2.1, expected degrees capped at 1000, so the background's own core stays small)
+    plus 50 planted communities of U[smin, smax] vertices at intra-density 0.9.
+    The default sizes are capped at 80 so that the single-threaded oracle counts
+    every k within minutes (sizes of 100 and more hold 1e8 and more maximal cliques
+    each)."""
+    return dense_core(n, mean, gamma, nc, smin, smax, p, seed, wmax)
 
 
 def config_powerlaw(seed: int = 2, n: int = 1_000_000, mean: float = 32.0,

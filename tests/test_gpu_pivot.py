@@ -88,3 +88,34 @@ def test_pivot_edge_cases(kc):
         assert got == (bc + [0] * 7)[:7]
         for k in (1, 2, 3, 4):
             assert kc.count(d, k, pivot=True) == (bc[k] if k < len(bc) else 0)
+
+
+def _densecore_fixture():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "densecore_count_all.txt")
+    head, counts = {}, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "c":
+                counts[int(parts[1])] = int(parts[2])
+            else:
+                head[parts[0]] = int(parts[1])
+    return head, counts
+
+
+def test_config_densecore_count_all(kc):
+    # the dense-core workload at full size (n = 500k, ~10M edges, 50 planted
+    # communities): every c_k against the oracle's counts stored by
+    # tests/golden/make_densecore_counts.py, in both root schemes
+    head, want = _densecore_fixture()
+    g = synth.config_densecore()
+    assert (g.n, g.m) == (head["n"], head["m"])
+    d = kc.orient(kc.to_device(g), kc.ORDER_DEGENERACY)
+    for scheme in (kc.SCHEME_VC, kc.SCHEME_EC):
+        got, omega = kc.count_all(d, pivot=True, scheme=scheme)
+        assert omega == head["omega"], scheme
+        assert got[:omega + 1] == [want[k] for k in range(omega + 1)], scheme
+        assert all(c == 0 for c in got[omega + 1:])
