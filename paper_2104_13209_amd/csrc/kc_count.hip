@@ -546,6 +546,9 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
     if (pivot_all >= 0) {
         KC_CHECK(hipMemsetAsync(w.counts, 0, 2 * sizeof(unsigned long long) * (w.binom_n + 1), s));
+        // frame queues of the light and the heavy launch
+        KC_CHECK(hipMemsetAsync(w.qctl, 0, sizeof(int) * kQueueCtlWords * 2, s));
+        KC_CHECK(hipMemsetAsync(w.qready, 0, sizeof(int) * kQueueCap * 2, s));
         int st0 = pivot_binom_table(w, s);
         if (st0 != KC_OK) return st0;
     }
@@ -705,6 +708,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         L.all = pivot_all == 1;
         L.ec = ec;
         L.stats = stats;
+        L.steal = !(o && (o->flags & KC_OPT_NO_HANDOFF));
         L.d_max = d->d_max;
         L.row_ptr = d->row_ptr;
         L.col = d->col;
@@ -856,6 +860,7 @@ extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* 
         int hctl[CC_WORDS];
         int st = run_count(d, 0, 1, o, w, scheme == KC_SCHEME_EC, 0ull, res, hctl, host, len, s);
         if (st != KC_OK) { delete[] host; return st; }
+        if (hctl[CC_FLAGS] & 2) { delete[] host; return KC_EDEVICE; }   // frame queue stalled
         ovf = (hctl[CC_FLAGS] & 1) != 0;
         for (int j = 3; j < len; j++) {
             if (host[2 * j] | host[2 * j + 1]) {

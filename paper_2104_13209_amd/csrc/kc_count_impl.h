@@ -12,6 +12,11 @@ constexpr int kWidthLists = 6;         // root lists by bitset words per row: 1,
 constexpr int kQueueCap = 16384;        // lane walk: ring slots for subtrees handed between wavefronts (power of 2)
 constexpr int kItemWords = 36;          // queue item: root slot, path length, 2 spare, 32 words of R
 constexpr int kQueueCtlWords = 8;       // per width list: head, tail, pending, rooting, hungry
+// subtree queue control words, and its bounds
+constexpr int Q_HEAD = 0, Q_TAIL = 1, Q_PENDING = 2, Q_ROOTING = 3, Q_HUNGRY = 4;
+constexpr int kMaxWaiters = 256;                            // wavefronts that wait for handed-over work
+constexpr unsigned long long kStallTicks = 2000000000ull;   // 20 s at 100 MHz without queue progress
+constexpr int kReadySpins = 1 << 22;                        // wait for a reserved item's sequence word
 constexpr int kAccWords = 9 + 7 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, expansions, busy, start, end
 
 enum CountCtl {
@@ -116,6 +121,7 @@ struct PivLaunch {
     bool all;             // count every size
     bool ec;              // edge roots
     bool stats;
+    bool steal;           // hand saved frames to idle wavefronts (queue regions 0 and 1)
     int d_max;
     const int* row_ptr;
     const int* col;

@@ -32,11 +32,6 @@ constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
 constexpr int kStealEvery = 16;   // wavefront rounds (up to 8 lane steps each) between looks at the subtree queue
 constexpr int kInner = 8;         // lane-local steps per wavefront-level round
 constexpr int kStealMax = 8;      // subtrees handed over per look
-constexpr int kMaxWaiters = 256;  // wavefronts that wait for handed-over subtrees; the rest leave
-// queue control words
-constexpr int Q_HEAD = 0, Q_TAIL = 1, Q_PENDING = 2, Q_ROOTING = 3, Q_HUNGRY = 4;
-constexpr unsigned long long kStallTicks = 2000000000ull;   // 20 s at 100 MHz without queue progress
-constexpr int kReadySpins = 1 << 22;                         // wait for a reserved item's flag
 
 struct LaneParams {
     int k;

@@ -47,7 +47,13 @@ struct PivParams {
     unsigned int* gstack;
     size_t slab_words;
     unsigned long long* stats;               // [nodes, words]
+    bool steal;                              // hand saved frames to idle wavefronts
+    int* qctl;                               // queue control words (zero at launch)
+    int* qready;                             // ring slot sequence words (zero at launch)
+    unsigned int* qitems;                    // kItemWords per ring slot
 };
+
+constexpr int kPivStealEvery = 64;           // tree nodes between looks at the frame queue
 
 // ------------------------------------------------------------ binomials
 
@@ -181,25 +187,122 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
         }
     };
 
+    // Work: the roots of this list, then frames that other wavefronts handed
+    // over.  A busy wavefront that sees waiting wavefronts (and fewer queued
+    // frames than waiters) hands over its shallowest saved frame that still has
+    // children left: (root slot, I, P, rest of P, pivot, pivots, holds); it then
+    // clears that frame's rest of P, so the children are walked exactly once.
+    // Termination and the ring protocol are those of the lane walk's subtree
+    // queue: a count of wavefronts in the root phase and a count of published,
+    // unfinished frames, both read zero (root phase first) when all work is done.
+    constexpr bool CAN_STEAL = 4 + 3 * MAXW <= kItemWords;
+    const bool steal = CAN_STEAL && P.steal;
+    int* q = P.qctl;
+    if (steal && (ld_acquire(P.flags) & 2)) return;   // an earlier launch of the call stalled
+    if (steal && lane == 0) atomicAdd(&q[Q_ROOTING], 1);
+    bool roots_done = false, hungry = false;
+    int cur = -1, chk = 0;                            // root whose S and rows are in LDS
     for (;;) {
-        int root = 0;
-        if (lane == 0) root = atomicAdd(P.head, 1);
-        root = __shfl(root, 0);
-        if (root >= nroots) break;
-        const int rid = P.roots[root];
-        extract_set<1, EC>(rid, P.row_ptr, P.col, P.src, lane, S, &ctl[1]);
+        int slot = -1;
+        bool from_item = false;
+        unsigned int I = 0, Po = 0, Pr = 0;
+        int np = 0, nh = nh_root, level = 0, p = 0;
+        if (!roots_done) {
+            int root = 0;
+            if (lane == 0) root = atomicAdd(P.head, 1);
+            root = __shfl(root, 0);
+            if (root < nroots) {
+                slot = root;
+            } else {
+                roots_done = true;
+                if (!steal) break;
+                if (lane == 0) __hip_atomic_fetch_add(&q[Q_ROOTING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                int stay = 1;
+                if (lane == 0 && atomicAdd(&q[Q_HUNGRY], 1) >= kMaxWaiters) {
+                    atomicAdd(&q[Q_HUNGRY], -1);
+                    stay = 0;
+                }
+                stay = __shfl(stay, 0);
+                if (!stay) break;
+                hungry = true;
+                continue;
+            }
+        } else {
+            // wait for a queued frame, or for the end of all work
+            int idx = -1, state = 0, backoff = 0;
+            unsigned long long sig = ~0ull, t_sig = 0;
+            for (;;) {
+                if (lane == 0) {
+                    const int h = ld_acquire(&q[Q_HEAD]);
+                    const int t = ld_acquire(&q[Q_TAIL]);
+                    if (h < t) {
+                        if (atomicCAS(&q[Q_HEAD], h, h + 1) == h) idx = h;
+                    } else {
+                        const int rooting = __hip_atomic_load(&q[Q_ROOTING], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        const int pend = __hip_atomic_load(&q[Q_PENDING], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+                        const unsigned long long sg = (static_cast<unsigned long long>(static_cast<unsigned int>(t)) << 40) ^
+                                                      (static_cast<unsigned long long>(static_cast<unsigned int>(pend)) << 20) ^
+                                                      static_cast<unsigned int>(rooting);
+                        if (sg != sig) { sig = sg; t_sig = now; }
+                        if ((rooting == 0 && pend == 0) || (ld_acquire(P.flags) & 2)) state = 1;
+                        else if (now - t_sig > kStallTicks) state = 2;
+                    }
+                }
+                idx = __shfl(idx, 0);
+                state = __shfl(state, 0);
+                if (idx >= 0 || state != 0) break;
+                if (backoff < 5) backoff++;
+                for (int i = 0; i < (1 << backoff); i++) __builtin_amdgcn_s_sleep(127);
+            }
+            if (idx < 0) {
+                if (state == 2 && lane == 0) atomicOr(P.flags, 2);
+                break;
+            }
+            if (hungry && lane == 0) atomicAdd(&q[Q_HUNGRY], -1);
+            hungry = false;
+            const int qs = idx & (kQueueCap - 1);
+            const int gen = idx - qs;
+            const unsigned int* it = P.qitems + static_cast<size_t>(qs) * kItemWords;
+            int ok = 1;
+            if (lane == 0) {
+                int spins = 0;
+                while (__hip_atomic_load(&P.qready[qs], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen + 1) {
+                    if (++spins > kReadySpins) { ok = 0; break; }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            ok = __shfl(ok, 0);
+            if (!ok) {
+                if (lane == 0) atomicOr(P.flags, 2);
+                break;
+            }
+            slot = static_cast<int>(ld_acquire(&it[0]));
+            p = static_cast<int>(ld_acquire(&it[1]));
+            np = static_cast<int>(ld_acquire(&it[2]));
+            nh = static_cast<int>(ld_acquire(&it[3]));
+            if (lane < MAXW) {
+                I = ld_acquire(&it[4 + lane]);
+                Po = ld_acquire(&it[4 + MAXW + lane]);
+                Pr = ld_acquire(&it[4 + 2 * MAXW + lane]);
+            }
+            if (lane == 0)   // the wavefront's loads are done: the slot is free for the next generation
+                __hip_atomic_store(&P.qready[qs], gen + kQueueCap, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            from_item = true;
+        }
+        // the root's S and rows (kept when the next frame is of the same root)
+        if (slot != cur) {
+            extract_set<1, EC>(P.roots[slot], P.row_ptr, P.col, P.src, lane, S, &ctl[1]);
+            extract_rows<1, true>(ctl[1], P.row_ptr, P.col, lane, S, A, stride);
+            cur = slot;
+        }
         const int s = ctl[1];
-        extract_rows<1, true>(s, P.row_ptr, P.col, lane, S, A, stride);
-        if (s == 0) {
+        const int W = (s + 31) >> 5;
+        if (!from_item && s == 0) {
             leaf(0, nh_root);
             wave_sync_lds();
             continue;
         }
-        const int W = (s + 31) >> 5;
-
-        unsigned int I = 0, Po = 0, Pr = 0;
-        if (lane < W) I = (lane < W - 1 || (s & 31) == 0) ? ~0u : ((1u << (s & 31)) - 1u);
-        int np = 0, nh = nh_root, level = 0, p = 0;
 
         // choose the pivot of the node with candidates I; sets p, Po, Pr
         auto enter = [&]() {
@@ -230,8 +333,78 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             wave_sync_lds();
         };
 
-        enter();
+        if (!from_item) {
+            if (lane < W) I = (lane < W - 1 || (s & 31) == 0) ? ~0u : ((1u << (s & 31)) - 1u);
+            enter();
+        }
         for (;;) {
+            if (steal && ++chk == kPivStealEvery) {
+                chk = 0;
+                int want = 0;
+                if (lane == 0) {
+                    want = ld_acquire(&q[Q_HUNGRY]);
+                    if (want > 0) want -= ld_acquire(&q[Q_TAIL]) - ld_acquire(&q[Q_HEAD]);
+                }
+                want = __shfl(want, 0);
+                int fl = -1;
+                if (want > 0) {
+                    // the shallowest saved frame with children left
+                    for (int l = 0; l < level; l++) {
+                        const unsigned int pr = lane < MAXW ? st_load<GST>(stk + static_cast<size_t>(l) * LV + 2 * MAXW + lane) : 0u;
+                        if (__ballot(pr != 0u) != 0ull) { fl = l; break; }
+                    }
+                }
+                if (fl >= 0) {
+                    int t0 = -1;
+                    if (lane == 0) {
+                        const int h = ld_acquire(&q[Q_HEAD]);
+                        int t = ld_acquire(&q[Q_TAIL]);
+                        for (;;) {
+                            if (t + 1 - h > kQueueCap) { t = -1; break; }
+                            const int prev = atomicCAS(&q[Q_TAIL], t, t + 1);
+                            if (prev == t) break;
+                            t = prev;
+                        }
+                        if (t >= 0) atomicAdd(&q[Q_PENDING], 1);
+                        t0 = t;
+                    }
+                    t0 = __shfl(t0, 0);
+                    if (t0 >= 0) {
+                        const int qs = t0 & (kQueueCap - 1);
+                        const int gen = t0 - qs;
+                        unsigned int* it = P.qitems + static_cast<size_t>(qs) * kItemWords;
+                        int ok = 1;
+                        if (lane == 0) {
+                            int spins = 0;
+                            while (__hip_atomic_load(&P.qready[qs], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen) {
+                                if (++spins > kReadySpins) { ok = 0; break; }
+                                __builtin_amdgcn_s_sleep(2);
+                            }
+                        }
+                        ok = __shfl(ok, 0);
+                        if (!ok) {
+                            if (lane == 0) atomicOr(P.flags, 2);
+                        } else {
+                            unsigned int* f = stk + static_cast<size_t>(fl) * LV;
+                            if (lane < MAXW) {
+                                it[4 + lane] = st_load<GST>(f + lane);
+                                it[4 + MAXW + lane] = st_load<GST>(f + MAXW + lane);
+                                it[4 + 2 * MAXW + lane] = st_load<GST>(f + 2 * MAXW + lane);
+                            }
+                            if (lane == 0) {
+                                it[0] = static_cast<unsigned int>(slot);
+                                it[1] = st_load<GST>(f + 3 * MAXW);
+                                it[2] = st_load<GST>(f + 3 * MAXW + 1);
+                                it[3] = st_load<GST>(f + 3 * MAXW + 2);
+                            }
+                            // the frame's remaining children now belong to the item
+                            if (lane < MAXW) f[2 * MAXW + lane] = 0u;
+                            if (lane == 0)
+                                __hip_atomic_store(&P.qready[qs], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
             const unsigned long long bal = __ballot(Pr != 0u);
             if (bal == 0ull) {
                 if (level == 0) break;
@@ -281,7 +454,15 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             }
         }
         wave_sync_lds();
+        if (from_item && lane == 0)
+            __hip_atomic_fetch_add(&q[Q_PENDING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (from_item) {
+            // back to waiting for frames
+            if (lane == 0) atomicAdd(&q[Q_HUNGRY], 1);
+            hungry = true;
+        }
     }
+    if (hungry && lane == 0) atomicAdd(&q[Q_HUNGRY], -1);
 
     // flush
     if (!ALL) {
@@ -355,6 +536,10 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
     P.big = L.w.big;
     P.gstack = L.w.gstack;
     P.slab_words = L.w.slab_words;
+    P.steal = L.steal;
+    P.qctl = L.w.qctl + kQueueCtlWords * (heavy ? 1 : 0);
+    P.qready = L.w.qready + static_cast<size_t>(kQueueCap) * (heavy ? 1 : 0);
+    P.qitems = L.w.qitems + static_cast<size_t>(kQueueCap) * kItemWords * (heavy ? 1 : 0);
     if (!heavy) {
         P.s_cap = kLightCap;
         P.roots = L.w.light;
