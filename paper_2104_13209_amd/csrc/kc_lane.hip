@@ -31,6 +31,7 @@ constexpr int kPairChunk = 64;    // pair tasks claimed per global atomic
 constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
 constexpr int kStealEvery = 16;   // wavefront rounds (up to 8 lane steps each) between looks at the subtree queue
 constexpr int kInner = 8;         // lane-local steps per wavefront-level round
+constexpr int kStealAfter = 256;  // rounds on the current root or subtree before it may hand over
 constexpr int kStealMax = 8;      // subtrees handed over per look
 
 struct LaneParams {
@@ -228,7 +229,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
         p = item_p;
     }
     const bool steal = PAIR && P.steal && P.counts[P.list] < 2 * static_cast<int>(gridDim.x);
-    int chk = 0;
+    int chk = 0, run_rounds = 0;   // only walks that have already run long hand work over
     int next_task = 0;                               // vertex tasks: wave counter
     int tq = 0, tq_end = 0;                          // pair tasks: claimed, unassigned range
     bool pq_done = false;                            // pair tasks: root counter exhausted
@@ -381,7 +382,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
         }
         // subtree queue: when wavefronts wait for work (more than are queued),
         // hand over the shallowest saved levels of up to kStealMax lanes
-        if (steal && ++chk == kStealEvery) {
+        if (steal && ++chk == kStealEvery && (run_rounds += kStealEvery) >= kStealAfter) {
             chk = 0;
             int want = 0;
             if (lane == 0) {
@@ -435,6 +436,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                 }
             }
         }
+        if (chk == kStealEvery) chk = 0;
         // done with this root when no lane holds work and no task is left
         bool busy = false;
 #pragma unroll

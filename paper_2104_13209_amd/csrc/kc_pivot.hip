@@ -54,6 +54,7 @@ struct PivParams {
 };
 
 constexpr int kPivStealEvery = 64;           // tree nodes between looks at the frame queue
+constexpr int kPivStealAfter = 4096;         // nodes of the current root or frame before it may hand over
 
 // ------------------------------------------------------------ binomials
 
@@ -337,8 +338,11 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             if (lane < W) I = (lane < W - 1 || (s & 31) == 0) ? ~0u : ((1u << (s & 31)) - 1u);
             enter();
         }
+        // only trees that have already run long hand work over: short ones would
+        // cost a consumer more (a root extraction) than they save
+        int run_nodes = 0;
         for (;;) {
-            if (steal && ++chk == kPivStealEvery) {
+            if (steal && ++chk == kPivStealEvery && (run_nodes += kPivStealEvery) >= kPivStealAfter) {
                 chk = 0;
                 int want = 0;
                 if (lane == 0) {
@@ -405,6 +409,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                     }
                 }
             }
+            if (chk == kPivStealEvery) chk = 0;
             const unsigned long long bal = __ballot(Pr != 0u);
             if (bal == 0ull) {
                 if (level == 0) break;

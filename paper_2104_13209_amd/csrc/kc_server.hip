@@ -126,9 +126,10 @@ struct kc_server {
             }
             q->t_start = kc::now_s();
             const kc_dag* d = &dags[q->graph];
-            // concurrency comes from the other queries: keep each count on its worker's stream
+            // concurrency comes from the other queries: keep each count on its worker's
+            // stream, and let idle wavefronts leave instead of waiting for handoffs
             kc_opts o{};
-            o.flags = KC_OPT_SINGLE_STREAM;
+            o.flags = KC_OPT_SINGLE_STREAM | KC_OPT_NO_HANDOFF;
             q->status = kc_count(d, q->k, q->pivot, &q->count, arena_mem + q->off, q->need, &o, s);
             q->t_done = kc::now_s();
             {
