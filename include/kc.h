@@ -161,7 +161,13 @@ KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t pivot, cons
  *               count is 2^64 or more.
  *   pivot != 0: hybrid pivoting traversal (Fig. 3, Sec. 2.3); 128-bit count,
  *               KC_EOVERFLOW at 2^128 or more.
- * k < 1 is KC_EINVAL; k = 1 gives n and k = 2 gives m.  Synchronises `stream`. */
+ * k < 1 is KC_EINVAL; k = 1 gives n and k = 2 gives m.  Synchronises `stream`.
+ * Deep non-pivot counts run the widest root list on an auxiliary stream of the
+ * library's own (fork and join by events on `stream`) unless KC_OPT_SINGLE_STREAM
+ * is set; wavefronts hand work to idle ones through the workspace's queues unless
+ * KC_OPT_NO_HANDOFF is set.  KC_EDEVICE is returned when such a queue stops making
+ * progress for 20 s (no count is valid then).  One workspace serves one call at a
+ * time. */
 KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
                         size_t ws_bytes, const kc_opts* o, void* stream);
 

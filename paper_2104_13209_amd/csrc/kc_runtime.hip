@@ -1,5 +1,6 @@
 // Process-wide runtime helpers of libkc: device properties, the side-stream
 // pool and status text.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -8,19 +9,22 @@
 
 namespace kc {
 
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_cus[kMaxDevices];   // 0 = not read yet (zero-initialised: static storage)
+}  // namespace
+
 int device_cus() {
-    static int cached_dev = -1, cached_cus = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (dev != cached_dev) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
+    if (dev < 0 || dev >= kMaxDevices) return 256;
+    int cus = g_cus[dev].load(std::memory_order_relaxed);
+    if (cus == 0) {
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        cached_cus = cus;
-        cached_dev = dev;
+        g_cus[dev].store(cus, std::memory_order_relaxed);   // every thread computes the same value
     }
-    return cached_cus;
+    return cus;
 }
 
 namespace {
