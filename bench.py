@@ -37,25 +37,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(k, width_list):
-    """HBM bytes of one lane-walk launch (width list, k) from the committed
-    FETCH_SIZE / WRITE_SIZE record, or None when there is none or the native
-    sources changed since the counters were taken."""
-    import glob
+# sources of the lane-walk launches (kernel, launch set-up, shared device code)
+LANE_SOURCES = ("kc_count.hip", "kc_count_impl.h", "kc_extract.h", "kc_internal.h", "kc_lane.hip")
+
+
+def lane_sources_sha256():
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(here, "paper_2104_13209_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in LANE_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(here, "paper_2104_13209_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(k, width_list):
+    """HBM bytes of one lane-walk launch (width list, k) from the committed
+    FETCH_SIZE / WRITE_SIZE record, or None when there is none or the lane-walk
+    sources changed since the counters were taken."""
+    here = os.path.dirname(os.path.abspath(__file__))
     try:
         with open(os.path.join(here, "profiles", "k_lane_powerlaw_k10_hbm_counters.md")) as fh:
             line = next(x for x in fh if x.startswith("traffic-record: "))
     except (OSError, StopIteration):
         return None
     rec = json.loads(line[len("traffic-record: "):])
-    if rec.get("csrc_sha256") != h.hexdigest() or rec.get("k") != k:
+    if rec.get("lane_sources_sha256") != lane_sources_sha256() or rec.get("k") != k:
         return None
     b = rec["bytes_per_launch_by_width_list"].get(str(width_list))
     return int(b) if b is not None else None
