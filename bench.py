@@ -167,6 +167,35 @@ def bench_batched(kc, ngraphs, k, reps):
     }
 
 
+def bench_small(kc, reps):
+    """The small plain-method workload: latency of orientation and of the k = 4
+    count (degree order, vertex roots), the count checked against the oracle."""
+    import torch
+    import oracle
+    import synth
+    g = synth.config_small()
+    dev = torch.device("cuda:0")
+    csr = kc.to_device(g, dev)
+    d = kc.orient(csr, kc.ORDER_DEGREE)
+    c = kc.count(d, 4, scheme=kc.SCHEME_VC)
+    torch.cuda.synchronize()
+    t_or, t_ct = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        d = kc.orient(csr, kc.ORDER_DEGREE)
+        t1 = time.perf_counter()
+        c = kc.count(d, 4, scheme=kc.SCHEME_VC)
+        t2 = time.perf_counter()
+        t_or.append((t1 - t0) * 1e3)
+        t_ct.append((t2 - t1) * 1e3)
+    want = oracle.count(oracle.orient(g, oracle.DEGREE), 4, False, oracle.VC)
+    return {"workload": "Erdos-Renyi G(2000, 0.01), seed 1; k = 4, degree order, vertex roots, non-pivot",
+            "n": g.n, "m": g.m, "count": str(c), "matches_oracle": c == want,
+            "orient_ms_p50": round(sorted(t_or)[len(t_or) // 2], 3),
+            "count_ms_p50": round(sorted(t_ct)[len(t_ct) // 2], 3),
+            "note": "launch- and latency-bound: host wall time per call, inputs resident"}
+
+
 def bench_densecore(kc, reps):
     """Pivot count-all (every k, 128-bit) on the dense-core workload, with the
     counts compared to the oracle's stored in tests/golden/."""
@@ -462,6 +491,9 @@ def main():
         batched = bench_batched(kc, args.batch_graphs, args.batch_k, args.batch_reps)
         log("batched: %.0f graphs/s vs plain %.0f graphs/s" % (batched["graphs_per_s"], batched["plain_graphs_per_s"]))
 
+    small = bench_small(kc, 20)
+    log("small: orient %.3f ms, count %.3f ms" % (small["orient_ms_p50"], small["count_ms_p50"]))
+
     dense = None
     if not args.no_dense:
         log("dense-core form ...")
@@ -504,6 +536,7 @@ def main():
         "per_k": per_k,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "small": small,
         "batched": batched,
         "dense_core": dense,
         "served": served,
