@@ -169,7 +169,9 @@ def bench_batched(kc, ngraphs, k, reps):
 
 def bench_small(kc, reps):
     """The small plain-method workload: latency of orientation and of the k = 4
-    count (degree order, vertex roots), the count checked against the oracle."""
+    count (degree order, vertex roots), the count checked against the oracle.
+    Its 4-clique count is tiny (about 0.7 expected), so the triangle count of
+    the same graph is checked as well."""
     import torch
     import oracle
     import synth
@@ -188,9 +190,13 @@ def bench_small(kc, reps):
         t2 = time.perf_counter()
         t_or.append((t1 - t0) * 1e3)
         t_ct.append((t2 - t1) * 1e3)
-    want = oracle.count(oracle.orient(g, oracle.DEGREE), 4, False, oracle.VC)
+    od = oracle.orient(g, oracle.DEGREE)
+    want = oracle.count(od, 4, False, oracle.VC)
+    c3 = kc.count(d, 3, scheme=kc.SCHEME_VC)
+    want3 = oracle.count(od, 3, False, oracle.VC)
     return {"workload": "Erdos-Renyi G(2000, 0.01), seed 1; k = 4, degree order, vertex roots, non-pivot",
-            "n": g.n, "m": g.m, "count": str(c), "matches_oracle": c == want,
+            "n": g.n, "m": g.m, "count": str(c), "triangles": str(c3),
+            "matches_oracle": c == want and c3 == want3,
             "orient_ms_p50": round(sorted(t_or)[len(t_or) // 2], 3),
             "count_ms_p50": round(sorted(t_ct)[len(t_ct) // 2], 3),
             "note": "launch- and latency-bound: host wall time per call, inputs resident"}
