@@ -171,6 +171,27 @@ KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t pivot, cons
 KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
                         size_t ws_bytes, const kc_opts* o, void* stream);
 
+/* Size of the fixed device scratch array behind kc_count_noalloc (64 MiB per
+ * GPU the library runs on, held until the process ends). */
+#define KC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* kc_count without a caller workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and statuses as kc_count; the
+ * workspace is a file-scope device array of KC_NOALLOC_SCRATCH_BYTES, one per
+ * GPU, whose address is looked up once per device on the first call made with
+ * that device current.  The call allocates nothing (no hipMalloc, no stream or
+ * event creation): it always runs single-stream (KC_OPT_SINGLE_STREAM is
+ * forced) and ignores kc_opts.profile and collect_stats.  Returns KC_ENOMEM when
+ * kc_count_workspace() for this DAG exceeds KC_NOALLOC_SCRATCH_BYTES (about
+ * 16 bytes per root plus 5 MB: non-pivot counts of graphs up to roughly 3.8M
+ * edges).  Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each call re-initialises what it reads): calls that overlap in time on
+ * the same GPU, from any thread or stream, race and must be serialised by the
+ * caller.  Synchronises `stream`. */
+KC_API int32_t kc_count_noalloc(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count,
+                                const kc_opts* o, void* stream);
+
 /* counts[j] = number of j-cliques for j = 0..cap (host array of cap+1), with
  * counts[0] = 1 (the empty clique), counts[1] = n, counts[2] = m; *omega = the
  * largest j with counts[j] > 0 (the clique number).  pivot != 0 uses pivoting

@@ -94,6 +94,9 @@ def lib():
         L.kc_count_all.argtypes = [P(_Dag), ctypes.c_int32, P(_U128), ctypes.c_int32, P(ctypes.c_int32),
                                    ctypes.c_void_p, ctypes.c_size_t, P(_Opts), ctypes.c_void_p]
         L.kc_count_all.restype = ctypes.c_int32
+        L.kc_count_noalloc.argtypes = [P(_Dag), ctypes.c_int32, ctypes.c_int32, P(_U128), P(_Opts),
+                                       ctypes.c_void_p]
+        L.kc_count_noalloc.restype = ctypes.c_int32
         L.kc_strerror.argtypes = [ctypes.c_int32]
         L.kc_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -254,6 +257,24 @@ def count_all(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = 
     if st != OK:
         raise KcError(st, "kc_count_all")
     return [int(r.lo) | (int(r.hi) << 64) for r in res], int(om.value)
+
+
+def count_noalloc_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, stream=None):
+    """(status, count) of kc_count_noalloc: kc_count on the library's fixed
+    device scratch instead of a caller workspace (no allocation anywhere)."""
+    cd = d._c()
+    o = _opts(scheme, 0, 0)
+    res = _U128(0, 0)
+    st = lib().kc_count_noalloc(ctypes.byref(cd), k, int(bool(pivot)), ctypes.byref(res), ctypes.byref(o),
+                                _stream_handle(stream))
+    return st, int(res.lo) | (int(res.hi) << 64)
+
+
+def count_noalloc(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, stream=None) -> int:
+    st, val = count_noalloc_status(d, k, pivot, scheme, stream)
+    if st != OK:
+        raise KcError(st, "kc_count_noalloc")
+    return val
 
 
 def dag_to_host(d: Dag):

@@ -26,6 +26,7 @@
 // Every lane keeps its own 64-bit partial count; wavefronts reduce them exactly
 // into a 128-bit device counter when they exit.
 #include <climits>
+#include <mutex>
 #include <new>
 
 #include "kc_extract.h"
@@ -802,8 +803,13 @@ extern "C" KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t 
     return bytes;
 }
 
-extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
-                                   size_t ws_bytes, const kc_opts* o, void* stream) {
+namespace kc {
+namespace {
+
+// kc_count's body over a workspace the caller (or the fixed scratch array)
+// provides.
+int count_with_ws(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws, size_t ws_bytes,
+                  const kc_opts* o, hipStream_t s) {
     if (!valid_dag(d) || !count || k < 1) return KC_EINVAL;
     count->lo = count->hi = 0;
     const unsigned long long preload = o ? o->test_preload : 0ull;
@@ -819,7 +825,6 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     size_t need = 0;
     CountWs w = carve_count(ws, d, pivot != 0, &need);
     if (!ws || ws_bytes < need) return KC_ENOMEM;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     if (k > d->d_max + 1 || d->m == 0) {
         count->lo = preload;
         return KC_OK;
@@ -836,6 +841,60 @@ extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc
     if (pivot && (hctl[CC_FLAGS] & 1)) return KC_EOVERFLOW;
     if (!pivot && res[1] != 0) return KC_EOVERFLOW;
     return KC_OK;
+}
+
+// Fixed device scratch of kc_count_noalloc: one copy per GPU, kept until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = static_cast<size_t>(KC_NOALLOC_SCRATCH_BYTES);
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices];   // device address of `scratch` per device (null = not looked up)
+
+int scratch_ptr(void** out) {
+    int dev = 0;
+    KC_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return KC_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        KC_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return KC_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KC_OK;
+}
+
+}  // namespace
+}  // namespace kc
+
+extern "C" KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
+                                   size_t ws_bytes, const kc_opts* o, void* stream) {
+    return count_with_ws(d, k, pivot, count, ws, ws_bytes, o, static_cast<hipStream_t>(stream));
+}
+
+extern "C" KC_API int32_t kc_count_noalloc(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count,
+                                           const kc_opts* o, void* stream) {
+    if (!valid_dag(d) || !count || k < 1) return KC_EINVAL;
+    // no side stream (its pool creates streams on first use) and no profile
+    // (its events are created on first use): only the caller's stream is used
+    kc_opts local{};
+    if (o) local = *o;
+    local.flags |= KC_OPT_SINGLE_STREAM;
+    local.profile = nullptr;
+    local.collect_stats = 0;
+    void* ws = nullptr;
+    if (k >= 3) {
+        size_t need = 0;
+        carve_count(nullptr, d, pivot != 0, &need);
+        if (need > kScratchBytes) return KC_ENOMEM;   // beyond the fixed scratch
+        const int st = scratch_ptr(&ws);
+        if (st != KC_OK) return st;
+    }
+    return count_with_ws(d, k, pivot, count, ws, kScratchBytes, &local, static_cast<hipStream_t>(stream));
 }
 
 extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,
