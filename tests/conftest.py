@@ -27,3 +27,20 @@ def kc():
     import paper_2104_13209_amd as kcmod
     kcmod.lib()
     return kcmod
+
+
+def load_counts(name):
+    """A stored count fixture under tests/golden/: ({header: int}, {k: c_k}, {k: nodes})."""
+    head, counts, nodes = {}, {}, {}
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "c":
+                counts[int(parts[1])] = int(parts[2])
+            elif parts[0] == "nodes":
+                nodes[int(parts[1])] = int(parts[2])
+            else:
+                head[parts[0]] = int(parts[1])
+    return head, counts, nodes

@@ -1,0 +1,62 @@
+"""The power-law workload at full size (Chung-Lu, n = 1,000,000, ~16M edges,
+degree exponent 2.1, seed 2) against the oracle's stored counts.
+
+The counts in tests/golden/powerlaw_counts.txt were written by
+tests/golden/make_powerlaw_counts.py with the oracle alone (degeneracy order,
+plain recursion of Fig. 2 over edge roots, split over host processes).  The GPU
+counts the same graph through the C ABI in the launch configuration the
+benchmark times (edge roots, degeneracy order, default scheduling) and with the
+scheduling switches off one at a time; every count must be equal.
+"""
+import math
+import os
+
+import pytest
+
+import synth
+from conftest import ROOT, load_counts
+
+pytestmark = pytest.mark.gpu
+
+N, MEAN = 1_000_000, 32.0
+
+
+@pytest.fixture(scope="module")
+def variant(kc):
+    head, want, _ = load_counts("powerlaw_counts.txt")
+    g = synth.config_powerlaw(n=N, wmax=math.sqrt(N * MEAN))
+    assert (g.n, g.m) == (head["n"], head["m"])
+    d = kc.orient(kc.to_device(g, "cuda:0"), kc.ORDER_DEGENERACY)
+    return d, want
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6, 7, 8, 9, 10])
+def test_powerlaw_counts_match_oracle(kc, variant, k):
+    d, want = variant
+    print("powerlaw w_max 5657: k=%d" % k, flush=True)
+    assert kc.count(d, k, pivot=False, scheme=kc.SCHEME_EC) == want[k]
+
+
+@pytest.mark.parametrize("k", [4, 7, 10])
+@pytest.mark.parametrize("mode", ["no_handoff", "single_stream"])
+def test_powerlaw_scheduling_switches(kc, variant, k, mode):
+    d, want = variant
+    print("powerlaw w_max 5657: k=%d %s" % (k, mode), flush=True)
+    got = kc.count(d, k, pivot=False, scheme=kc.SCHEME_EC, handoff=mode != "no_handoff",
+                   single_stream=mode == "single_stream")
+    assert got == want[k]
+
+
+def test_powerlaw_literal_wmax(kc):
+    # the graph with expected degrees capped at 20,000 as the configuration
+    # states (a saturated core of a few hundred vertices): c_3 and c_4
+    path = os.path.join(ROOT, "tests", "golden", "powerlaw_wmax20000_counts.txt")
+    if not os.path.exists(path):
+        pytest.skip("no stored counts for the w_max = 20000 graph")
+    head, want, _ = load_counts("powerlaw_wmax20000_counts.txt")
+    g = synth.config_powerlaw(n=N, wmax=20000.0)
+    assert (g.n, g.m) == (head["n"], head["m"])
+    d = kc.orient(kc.to_device(g, "cuda:0"), kc.ORDER_DEGENERACY)
+    for k in sorted(want):
+        print("powerlaw w_max 20000: k=%d" % k, flush=True)
+        assert kc.count(d, k, pivot=False, scheme=kc.SCHEME_EC) == want[k], k
