@@ -47,7 +47,7 @@ typedef enum kc_status {
     KC_ENOMEM = -2,        /* workspace too small                                */
     KC_EOVERFLOW = -3,     /* count does not fit the result width                */
     KC_EDEVICE = -4,       /* a HIP runtime call failed                          */
-    KC_ECANCELED = -5,     /* reserved                                           */
+    KC_ECANCELED = -5,     /* the caller's cancel flag stopped the count          */
     KC_EUNSUPPORTED = -6   /* graph exceeds a documented limit of this build     */
 } kc_status;
 
@@ -128,7 +128,21 @@ enum { KC_OPT_NO_HANDOFF = 1, KC_OPT_SINGLE_STREAM = 2 };
  * sub-wavefront group (1, 2, 4, 8, 16, 32 or 64; 0 = auto) (Sec. 3.5).
  * collect_stats and profile: see kc_profile.  flags: KC_OPT_* bits.
  * test_preload: added to the internal accumulator before counting; it exists
- * only so that tests can drive the 64-bit overflow path, and is 0 in normal use. */
+ * only so that tests can drive the 64-bit overflow path, and is 0 in normal use.
+ * cancel: NULL, or the address of an int32 that the traversal kernels read while
+ *   they run (device memory, or host memory allocated with hipHostMalloc and
+ *   mapped into the device's address space, which any host thread may write).
+ *   Once it holds a non-zero value the kernels stop taking work and the call
+ *   returns KC_ECANCELED with no valid count; the caller owns the flag and
+ *   resets it.  Kernels look at it when they start, every 32 wavefront rounds
+ *   of a walk (non-pivot) or 32 tree nodes (pivot), and between roots, so a
+ *   request takes effect within microseconds to milliseconds; calls that
+ *   launch no traversal (k <= 2, k > d_max + 1) ignore it.
+ * handoff_after, handoff_every: thresholds of the handoff between wavefronts
+ *   (0 = defaults: a walk may hand subtrees over after 256 wavefront rounds on
+ *   its current root or subtree and looks every 16 rounds; pivot trees after
+ *   4096 nodes, looking every 64).  Lower values exist for tests and
+ *   measurement; counts never depend on them. */
 typedef struct kc_opts {
     int32_t scheme;
     int32_t width;
@@ -136,6 +150,9 @@ typedef struct kc_opts {
     int32_t flags;
     uint64_t test_preload;
     kc_profile* profile;
+    const volatile int32_t* cancel;
+    int32_t handoff_after;
+    int32_t handoff_every;
 } kc_opts;
 
 /* Bytes of device workspace kc_orient needs for this input size and order. */
@@ -194,10 +211,12 @@ KC_API int32_t kc_count_noalloc(const kc_dag* d, int32_t k, int32_t pivot, kc_u1
 
 /* counts[j] = number of j-cliques for j = 0..cap (host array of cap+1), with
  * counts[0] = 1 (the empty clique), counts[1] = n, counts[2] = m; *omega = the
- * largest j with counts[j] > 0 (the clique number).  pivot != 0 uses pivoting
- * (Sec. 2.3); pivot == 0 walks the orientation tree with no depth bound.
- * Returns KC_EINVAL if cap < 2 and KC_EOVERFLOW if a count needs more than 128
- * bits.  Synchronises `stream`. */
+ * largest j with a j-clique (the clique number).  pivot != 0 uses one pivoting
+ * traversal for every size (Sec. 2.3).  pivot == 0 runs the graph-orientation
+ * traversal (Fig. 2) once per size, k = 3, 4, ..., until a size has no clique
+ * (at most d_max + 1), so its cost is one kc_count per size up to omega + 1
+ * whatever cap is.  Returns KC_EINVAL if cap < 2 and KC_EOVERFLOW if a count
+ * needs more than 128 bits.  Synchronises `stream`. */
 KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,
                             int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
                             void* stream);
@@ -272,11 +291,16 @@ typedef struct kc_query_result {
 
 KC_API int32_t kc_server_create(const kc_dag* dags, int32_t ndags, int32_t slots, uint64_t mem_budget,
                                 kc_server** out);
-/* Enqueue a query; *ticket identifies it.  Never blocks on the device. */
+/* Enqueue a query; *ticket identifies it.  Never blocks on the device.  Returns
+ * KC_ECANCELED once kc_server_destroy has begun. */
 KC_API int32_t kc_server_submit(kc_server* s, int32_t graph, int32_t k, int32_t pivot, uint64_t* ticket);
 /* Block until the query is done and return its result (each ticket once). */
 KC_API int32_t kc_server_wait(kc_server* s, uint64_t ticket, kc_query_result* res);
-/* Finish admitted queries, drop queries never admitted, free the server. */
+/* Shut the server down: queries never admitted end with status KC_ECANCELED
+ * (threads blocked on them in kc_server_wait wake up and receive that result),
+ * admitted queries run to completion, and the server's memory and streams are
+ * freed only after every thread inside kc_server_wait has returned.  No call on
+ * `s` may begin after kc_server_destroy has returned. */
 KC_API int32_t kc_server_destroy(kc_server* s);
 
 /* Static text for a status code. */

@@ -67,7 +67,9 @@ class Profile(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("width", ctypes.c_int32),
                 ("collect_stats", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("test_preload", ctypes.c_uint64), ("profile", ctypes.POINTER(Profile))]
+                ("test_preload", ctypes.c_uint64), ("profile", ctypes.POINTER(Profile)),
+                ("cancel", ctypes.c_void_p), ("handoff_after", ctypes.c_int32),
+                ("handoff_every", ctypes.c_int32)]
 
 
 _lib = None
@@ -193,9 +195,11 @@ def orient(g: Csr, order: int = ORDER_DEGREE, validate: bool = True, ws: torch.T
 
 
 def _opts(scheme: int, width: int, test_preload: int, profile: Profile | None = None,
-          collect_stats: bool = False, handoff: bool = True, single_stream: bool = False) -> _Opts:
+          collect_stats: bool = False, handoff: bool = True, single_stream: bool = False,
+          cancel: int = 0, handoff_after: int = 0, handoff_every: int = 0) -> _Opts:
     flags = (0 if handoff else OPT_NO_HANDOFF) | (OPT_SINGLE_STREAM if single_stream else 0)
-    o = _Opts(scheme, width, int(bool(collect_stats)), flags, test_preload, None)
+    o = _Opts(scheme, width, int(bool(collect_stats)), flags, test_preload, None,
+              ctypes.c_void_p(cancel or None), handoff_after, handoff_every)
     if profile is not None:
         o.profile = ctypes.pointer(profile)
     return o
@@ -210,11 +214,15 @@ def count_workspace_bytes(d: Dag, k: int, pivot: bool, scheme: int = 0, width: i
 def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
                  ws: torch.Tensor | None = None, test_preload: int = 0, stream=None,
                  profile: Profile | None = None, collect_stats: bool = False, handoff: bool = True,
-                 single_stream: bool = False):
-    """(status, count) of kc_count without raising."""
+                 single_stream: bool = False, cancel: int = 0, handoff_after: int = 0,
+                 handoff_every: int = 0):
+    """(status, count) of kc_count without raising.  cancel: address of a
+    device-readable int32 (device memory or mapped host memory) that stops the
+    count with ECANCELED once it holds a non-zero value."""
     L = lib()
     cd = d._c()
-    o = _opts(scheme, width, test_preload, profile, collect_stats, handoff, single_stream)
+    o = _opts(scheme, width, test_preload, profile, collect_stats, handoff, single_stream, cancel,
+              handoff_after, handoff_every)
     need = int(L.kc_count_workspace(ctypes.byref(cd), k, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)
@@ -226,27 +234,29 @@ def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
 
 def count(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
           ws: torch.Tensor | None = None, stream=None, profile: Profile | None = None,
-          collect_stats: bool = False, handoff: bool = True, single_stream: bool = False) -> int:
+          collect_stats: bool = False, handoff: bool = True, single_stream: bool = False,
+          handoff_after: int = 0, handoff_every: int = 0) -> int:
     """Number of k-cliques (kc_count); exact Python int.  handoff=False keeps
     every subtree on the wavefront that found it; single_stream=True keeps every
-    launch on `stream` (KC_OPT_* flags)."""
+    launch on `stream` (KC_OPT_* flags); handoff_after / handoff_every lower the
+    handoff thresholds (0 = defaults)."""
     st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream, profile, collect_stats, handoff,
-                           single_stream)
+                           single_stream, 0, handoff_after, handoff_every)
     if st != OK:
         raise KcError(st, "kc_count")
     return val
 
 
-def count_all(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = SCHEME_AUTO,
-              width: int = 0, ws: torch.Tensor | None = None, stream=None,
-              profile: Profile | None = None):
-    """([c_0, ..., c_cap], omega) for every clique size (kc_count_all)."""
+def count_all_status(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = SCHEME_AUTO,
+                     width: int = 0, ws: torch.Tensor | None = None, stream=None,
+                     profile: Profile | None = None, cancel: int = 0):
+    """(status, [c_0, ..., c_cap], omega) of kc_count_all without raising."""
     L = lib()
     if cap is None:
         cap = d.d_max + 2
     cap = max(int(cap), 2)
     cd = d._c()
-    o = _opts(scheme, width, 0, profile)
+    o = _opts(scheme, width, 0, profile, cancel=cancel)
     need = int(L.kc_count_workspace(ctypes.byref(cd), 0, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)
@@ -254,9 +264,17 @@ def count_all(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = 
     om = ctypes.c_int32(0)
     st = L.kc_count_all(ctypes.byref(cd), int(bool(pivot)), res, cap, ctypes.byref(om), _ptr(ws),
                         ws.numel(), ctypes.byref(o), _stream_handle(stream))
+    return st, [int(r.lo) | (int(r.hi) << 64) for r in res], int(om.value)
+
+
+def count_all(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = SCHEME_AUTO,
+              width: int = 0, ws: torch.Tensor | None = None, stream=None,
+              profile: Profile | None = None):
+    """([c_0, ..., c_cap], omega) for every clique size (kc_count_all)."""
+    st, counts, om = count_all_status(d, pivot, cap, scheme, width, ws, stream, profile)
     if st != OK:
         raise KcError(st, "kc_count_all")
-    return [int(r.lo) | (int(r.hi) << 64) for r in res], int(om.value)
+    return counts, om
 
 
 def count_noalloc_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, stream=None):

@@ -50,6 +50,8 @@ struct GoParams {
     unsigned long long* stats;       // [nodes, word_ops] (stats variant only)
     int s_cap;                       // LDS rows per team
     int levels;                      // stack levels per group
+    int* flags;                      // CC_FLAGS word (kFlagCanceled)
+    const int* cancel;               // caller's cancel flag (null: none)
 };
 
 __device__ __forceinline__ int ffs64(unsigned long long x) { return __ffsll(static_cast<long long>(x)) - 1; }
@@ -292,8 +294,15 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
     unsigned long long st_nodes = 0, st_words = 0;
 
     for (;;) {
-        // ---- fetch a root
-        if (tl == 0) ctl[2] = atomicAdd(P.head, 1);
+        // ---- fetch a root (none once the caller asked to cancel)
+        if (tl == 0) {
+            int r = atomicAdd(P.head, 1);
+            if (P.cancel && r < nroots && cancel_requested(P.cancel)) {
+                atomicOr(P.flags, kFlagCanceled);
+                r = nroots;
+            }
+            ctl[2] = r;
+        }
         team_sync<TW>();
         const int root = ctl[2];
         if (root >= nroots) break;
@@ -648,6 +657,11 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.qready = w.qready + static_cast<size_t>(kQueueCap) * lst;
             L.qitems = w.qitems + (on_side ? static_cast<size_t>(kQueueCap) * kItemWords : 0);
             L.flags = w.ctl + CC_FLAGS;
+            if (o) {
+                L.steal_every = o->handoff_every > 0 ? o->handoff_every : kLaneStealEvery;
+                L.steal_after = o->handoff_after > 0 ? o->handoff_after : kLaneStealAfter;
+                L.cancel = const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel));
+            }
             if (prof) KC_CHECK(hipEventRecord(pe->wl[2 * lst], ls));
             L.grid_out = &lane_grid[lst];
             if (on_side) side_launch = L;
@@ -685,6 +699,8 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         P.stats = w.acc + 2;
         P.s_cap = 0;
         P.levels = 0;
+        P.flags = w.ctl + CC_FLAGS;
+        P.cancel = o ? const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel)) : nullptr;
         P.roots = w.light;
         P.nroots = w.ctl + CC_LIGHT_N;
         P.head = w.ctl + CC_LIGHT_HEAD;
@@ -710,6 +726,11 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         L.ec = ec;
         L.stats = stats;
         L.steal = !(o && (o->flags & KC_OPT_NO_HANDOFF));
+        if (o) {
+            L.steal_every = o->handoff_every > 0 ? o->handoff_every : kPivStealEvery;
+            L.steal_after = o->handoff_after > 0 ? o->handoff_after : kPivStealAfter;
+            L.cancel = const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel));
+        }
         L.d_max = d->d_max;
         L.row_ptr = d->row_ptr;
         L.col = d->col;
@@ -835,10 +856,11 @@ int count_with_ws(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, voi
     int hctl[CC_WORDS];
     int st = run_count(d, k, pivot ? 0 : -1, o, w, scheme == KC_SCHEME_EC, preload, res, hctl, nullptr, 0, s);
     if (st != KC_OK) return st;
+    if (hctl[CC_FLAGS] & kFlagCanceled) return KC_ECANCELED;   // no valid count
+    if (hctl[CC_FLAGS] & kFlagStalled) return KC_EDEVICE;      // subtree queue stalled: no valid count
     count->lo = res[0];
     count->hi = pivot ? res[1] : 0ull;
-    if (hctl[CC_FLAGS] & 2) return KC_EDEVICE;   // subtree queue stalled: no valid count
-    if (pivot && (hctl[CC_FLAGS] & 1)) return KC_EOVERFLOW;
+    if (pivot && (hctl[CC_FLAGS] & kFlagBigBinom)) return KC_EOVERFLOW;
     if (!pivot && res[1] != 0) return KC_EOVERFLOW;
     return KC_OK;
 }
@@ -865,6 +887,46 @@ int scratch_ptr(void** out) {
         g_scratch_ptr[dev] = p;
     }
     *out = g_scratch_ptr[dev];
+    return KC_OK;
+}
+
+}  // namespace
+}  // namespace kc
+
+namespace kc {
+namespace {
+
+// kc_count_all without pivoting: the graph-orientation traversal (Fig. 2) is
+// run once per clique size, k = 3, 4, ..., until a size has no clique (at most
+// d_max + 1, the largest size an orientation allows); each count is the exact
+// 128-bit total of that traversal.
+int count_all_orient(const kc_dag* d, kc_u128* counts, int32_t cap, int32_t* omega, void* ws, size_t ws_bytes,
+                     const kc_opts* o, hipStream_t s) {
+    size_t need = 0;
+    CountWs w = carve_count(ws, d, false, &need);
+    if (!ws || ws_bytes < need) return KC_ENOMEM;
+    for (int j = 0; j <= cap; j++) counts[j].lo = counts[j].hi = 0;
+    counts[0].lo = 1;
+    counts[1].lo = static_cast<unsigned long long>(d->n);
+    counts[2].lo = static_cast<unsigned long long>(d->m);
+    int om = d->m > 0 ? 2 : (d->n > 0 ? 1 : 0);
+    for (int k = 3; d->m > 0 && k <= d->d_max + 1; k++) {
+        const int scheme = pick_scheme(o, k);
+        if (scheme != KC_SCHEME_VC && scheme != KC_SCHEME_EC) return KC_EINVAL;
+        unsigned long long res[kAccWords];
+        int hctl[CC_WORDS];
+        const int st = run_count(d, k, -1, o, w, scheme == KC_SCHEME_EC, 0ull, res, hctl, nullptr, 0, s);
+        if (st != KC_OK) return st;
+        if (hctl[CC_FLAGS] & kFlagCanceled) return KC_ECANCELED;
+        if (hctl[CC_FLAGS] & kFlagStalled) return KC_EDEVICE;
+        if ((res[0] | res[1]) == 0ull) break;
+        om = k;
+        if (k <= cap) {
+            counts[k].lo = res[0];
+            counts[k].hi = res[1];
+        }
+    }
+    *omega = om;
     return KC_OK;
 }
 
@@ -901,8 +963,8 @@ extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* 
                                        int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
                                        void* stream) {
     if (!valid_dag(d) || !counts || !omega || cap < 2) return KC_EINVAL;
-    if (!pivot) return KC_EUNSUPPORTED;
     if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    if (!pivot) return count_all_orient(d, counts, cap, omega, ws, ws_bytes, o, static_cast<hipStream_t>(stream));
     size_t need = 0;
     CountWs w = carve_count(ws, d, true, &need);
     if (!ws || ws_bytes < need) return KC_ENOMEM;
@@ -919,8 +981,9 @@ extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* 
         int hctl[CC_WORDS];
         int st = run_count(d, 0, 1, o, w, scheme == KC_SCHEME_EC, 0ull, res, hctl, host, len, s);
         if (st != KC_OK) { delete[] host; return st; }
-        if (hctl[CC_FLAGS] & 2) { delete[] host; return KC_EDEVICE; }   // frame queue stalled
-        ovf = (hctl[CC_FLAGS] & 1) != 0;
+        if (hctl[CC_FLAGS] & kFlagCanceled) { delete[] host; return KC_ECANCELED; }
+        if (hctl[CC_FLAGS] & kFlagStalled) { delete[] host; return KC_EDEVICE; }   // frame queue stalled
+        ovf = (hctl[CC_FLAGS] & kFlagBigBinom) != 0;
         for (int j = 3; j < len; j++) {
             if (host[2 * j] | host[2 * j + 1]) {
                 om = j;

@@ -17,6 +17,16 @@ constexpr int Q_HEAD = 0, Q_TAIL = 1, Q_PENDING = 2, Q_ROOTING = 3, Q_HUNGRY = 4
 constexpr int kMaxWaiters = 256;                            // wavefronts that wait for handed-over work
 constexpr unsigned long long kStallTicks = 2000000000ull;   // 20 s at 100 MHz without queue progress
 constexpr int kReadySpins = 1 << 22;                        // wait for a reserved item's sequence word
+// bits of the CC_FLAGS control word
+constexpr int kFlagBigBinom = 1;    // a binomial beyond 128 bits was used
+constexpr int kFlagStalled = 2;     // a work queue stopped making progress (no valid count)
+constexpr int kFlagCanceled = 4;    // the caller's cancel flag was seen (no valid count)
+// handoff thresholds (defaults; kc_opts may lower them for tests)
+constexpr int kLaneStealEvery = 16;    // lane walk: wavefront rounds between looks at the subtree queue
+constexpr int kLaneStealAfter = 256;   // lane walk: rounds on the current root or subtree before it may hand over
+constexpr int kPivStealEvery = 64;     // pivot: tree nodes between looks at the frame queue
+constexpr int kPivStealAfter = 4096;   // pivot: nodes of the current root or frame before it may hand over
+constexpr int kCancelEvery = 32;       // wavefront rounds (lane walk) or nodes (pivot) between cancel polls
 constexpr int kAccWords = 9 + 7 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, expansions, busy, start, end
 
 enum CountCtl {
@@ -24,7 +34,7 @@ enum CountCtl {
     CC_HEAVY_N = 1,      // heavy root count
     CC_LIGHT_HEAD = 2,   // light queue head
     CC_HEAVY_HEAD = 3,   // heavy queue head
-    CC_FLAGS = 4,        // bit 0: a binomial beyond 128 bits was used
+    CC_FLAGS = 4,        // kFlag* bits
     CC_WN0 = 8,          // width lists: root counts (8..13)
     CC_WC0 = 16,         // width lists: fill cursors (16..21)
     CC_WH0 = 24,         // width lists: queue heads (24..29)
@@ -122,6 +132,9 @@ struct PivLaunch {
     bool ec;              // edge roots
     bool stats;
     bool steal;           // hand saved frames to idle wavefronts (queue regions 0 and 1)
+    int steal_every = kPivStealEvery;
+    int steal_after = kPivStealAfter;
+    const int* cancel = nullptr;   // caller's cancel flag (null: none)
     int d_max;
     const int* row_ptr;
     const int* col;
@@ -154,7 +167,10 @@ struct LaneLaunch {
     int* qctl = nullptr;  // this list's queue control words (zero at launch)
     int* qready = nullptr;  // this list's ring slot sequence words (zero at launch)
     unsigned int* qitems = nullptr;
-    int* flags = nullptr;   // bit 1 set when the queue stalls (the count is then invalid)
+    int* flags = nullptr;   // CC_FLAGS word: kFlagStalled, kFlagCanceled
+    int steal_every = kLaneStealEvery;
+    int steal_after = kLaneStealAfter;
+    const int* cancel = nullptr;   // caller's cancel flag (null: none)
     unsigned long long* acc;
     unsigned long long* stats_ptr;
     unsigned long long* iters_ptr = nullptr;

@@ -68,6 +68,13 @@ __device__ __forceinline__ T ld_acquire(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Cooperative cancellation: the caller's flag (device memory or mapped host
+// memory) holds a non-zero value once the count should stop.  Read at system
+// scope so that a write by the host or another device queue is seen.
+__device__ __forceinline__ bool cancel_requested(const int* flag) {
+    return flag != nullptr && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+}
+
 // Exact unsigned 128-bit accumulation into device memory: lo receives x and a
 // carry out of lo goes to hi (both 64-bit atomics, so the sum is exact).
 // Returns true when the 128-bit total wrapped past 2^128.

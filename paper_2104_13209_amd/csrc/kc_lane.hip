@@ -29,9 +29,7 @@ namespace {
 
 constexpr int kPairChunk = 64;    // pair tasks claimed per global atomic
 constexpr int kRootChunk = 8;     // vertex-task roots claimed per global atomic
-constexpr int kStealEvery = 16;   // wavefront rounds (up to 8 lane steps each) between looks at the subtree queue
 constexpr int kInner = 8;         // lane-local steps per wavefront-level round
-constexpr int kStealAfter = 256;  // rounds on the current root or subtree before it may hand over
 constexpr int kStealMax = 8;      // subtrees handed over per look
 
 struct LaneParams {
@@ -60,8 +58,22 @@ struct LaneParams {
     int* qready;                    // per ring slot (zero at launch): g*cap free for the producer of
                                     // generation g, g*cap + 1 written, (g+1)*cap read
     unsigned int* qitems;           // kItemWords per item
-    int* flags;                     // bit 1: queue stalled
+    int* flags;                     // CC_FLAGS word: kFlagStalled, kFlagCanceled
+    int steal_every;                // wavefront rounds (up to kInner lane steps each) between queue looks
+    int steal_after;                // rounds on the current root or subtree before it may hand over
+    const int* cancel;              // caller's cancel flag (null: none)
 };
+
+// Poll the caller's cancel flag (lane 0, broadcast); on a request, mark the
+// call canceled.  Wave-uniform result.
+__device__ __forceinline__ bool poll_cancel(const int* cancel, int* flags) {
+    int c = 0;
+    if (__lane_id() == 0 && cancel_requested(cancel)) {
+        atomicOr(flags, kFlagCanceled);
+        c = 1;
+    }
+    return __shfl(c, 0) != 0;
+}
 
 // Batched counts: the lanes' partial counts of one root belong to one graph; add
 // them to that graph's 128-bit counter and restart from zero.
@@ -230,6 +242,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
     }
     const bool steal = PAIR && P.steal && P.counts[P.list] < 2 * static_cast<int>(gridDim.x);
     int chk = 0, run_rounds = 0;   // only walks that have already run long hand work over
+    int cpoll = 0;                 // rounds since the last look at the cancel flag
     int next_task = 0;                               // vertex tasks: wave counter
     int tq = 0, tq_end = 0;                          // pair tasks: claimed, unassigned range
     bool pq_done = false;                            // pair tasks: root counter exhausted
@@ -380,9 +393,14 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
             }
             wave_sync_lds();
         }
+        // cancellation: abandon the walk (the call's count is discarded)
+        if (P.cancel && ++cpoll == kCancelEvery) {
+            cpoll = 0;
+            if (poll_cancel(P.cancel, P.flags)) return;
+        }
         // subtree queue: when wavefronts wait for work (more than are queued),
         // hand over the shallowest saved levels of up to kStealMax lanes
-        if (steal && ++chk == kStealEvery && (run_rounds += kStealEvery) >= kStealAfter) {
+        if (steal && ++chk >= P.steal_every && (run_rounds += chk) >= P.steal_after) {
             chk = 0;
             int want = 0;
             if (lane == 0) {
@@ -422,7 +440,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                                ++spins <= kReadySpins)
                             __builtin_amdgcn_s_sleep(2);
                         if (spins > kReadySpins) {
-                            atomicOr(P.flags, 2);
+                            atomicOr(P.flags, kFlagStalled);
                         } else {
                             const unsigned int* f = stk + sbase * SLOT * 64 + lane;
                             it[0] = static_cast<unsigned int>(slot);
@@ -436,7 +454,7 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                 }
             }
         }
-        if (chk == kStealEvery) chk = 0;
+        if (chk >= P.steal_every) chk = 0;
         // done with this root when no lane holds work and no task is left
         bool busy = false;
 #pragma unroll
@@ -587,13 +605,15 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
     int* q = P.qctl;
     int cur = -1;                                   // root whose S and rows are in LDS
 
-    // an earlier launch of the same call stalled: give up at once
-    if (steal && (ld_acquire(P.flags) & 2)) return;
+    // an earlier launch of the same call stalled or was canceled: give up at once
+    if (P.flags && (ld_acquire(P.flags) & (kFlagStalled | kFlagCanceled))) return;
+    if (P.cancel && poll_cancel(P.cancel, P.flags)) return;
     unsigned long long acc = 0, nodes = 0, wsum = 0, iters = 0, exps = 0, idle = 0;
     const unsigned long long t_begin = STATS ? __builtin_amdgcn_s_memrealtime() : 0ull;
     if (steal && lane == 0) atomicAdd(&q[Q_ROOTING], 1);    // in the root phase
     bool helping = steal && P.helper;               // helpers own no roots (and no registry entry)
     int rq = 0, rq_end = 0;                         // claimed, unprocessed root range
+    int claims = 0;                                 // root claims since the last cancel poll
     constexpr int RC = PAIR ? 1 : kRootChunk;
 
     // ---------------------------------------------- root phase
@@ -641,6 +661,19 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
             __hip_atomic_store(&P.active[blockIdx.x], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (P.gacc) flush_root(P, graph, acc);
         wave_sync_lds();
+        if (P.cancel) {
+            // a walk that saw the request has marked it; otherwise look at the
+            // caller's flag every 64 roots
+            int c = 0;
+            if (lane == 0) {
+                c = (ld_acquire(P.flags) & kFlagCanceled) != 0;
+                if (!c && (++claims & 63) == 0 && cancel_requested(P.cancel)) {
+                    atomicOr(P.flags, kFlagCanceled);
+                    c = 1;
+                }
+            }
+            if (__shfl(c, 0)) break;
+        }
     }
 
     // ---------------------------------------------- queue phase
@@ -678,7 +711,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
                                                   (static_cast<unsigned long long>(static_cast<unsigned int>(pend)) << 20) ^
                                                   static_cast<unsigned int>(rooting);
                     if (sg != sig) { sig = sg; t_sig = now; }
-                    if ((rooting == 0 && pend == 0) || (ld_acquire(P.flags) & 2)) state = 1;
+                    if ((rooting == 0 && pend == 0) || (ld_acquire(P.flags) & (kFlagStalled | kFlagCanceled))) state = 1;
                     else if (now - t_sig > kStallTicks) state = 2;
                 }
             }
@@ -707,7 +740,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
                 }
                 ok = __shfl(ok, 0);
                 if (!ok) {
-                    if (lane == 0) atomicOr(P.flags, 2);
+                    if (lane == 0) atomicOr(P.flags, kFlagStalled);
                     break;
                 }
                 // copy the item into LDS (the pair-task prefix area, unused for a
@@ -728,7 +761,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
             }
             if (state == 1) break;
             if (state == 2) {
-                if (lane == 0) atomicOr(P.flags, 2);
+                if (lane == 0) atomicOr(P.flags, kFlagStalled);
                 break;
             }
             if (!hungry && lane == 0) atomicAdd(&q[Q_HUNGRY], 1);
@@ -825,6 +858,9 @@ int lane_launch(const LaneLaunch& L, hipStream_t s) {
     P.qready = L.qready;
     P.qitems = L.qitems;
     P.flags = L.flags;
+    P.steal_every = L.steal_every > 0 ? L.steal_every : kLaneStealEvery;
+    P.steal_after = L.steal_after > 0 ? L.steal_after : kLaneStealAfter;
+    P.cancel = L.flags ? L.cancel : nullptr;   // a cancel request is recorded in the flags word
     const int p0 = L.ec ? 3 : 2;
     // pair tasks start at path length p0 + 1; vertex tasks at p0.  Saved levels
     // are needed for path lengths below k - 2.

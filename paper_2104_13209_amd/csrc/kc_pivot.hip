@@ -51,10 +51,10 @@ struct PivParams {
     int* qctl;                               // queue control words (zero at launch)
     int* qready;                             // ring slot sequence words (zero at launch)
     unsigned int* qitems;                    // kItemWords per ring slot
+    int steal_every;                         // tree nodes between looks at the frame queue
+    int steal_after;                         // nodes of the current root or frame before it may hand over
+    const int* cancel;                       // caller's cancel flag (null: none)
 };
-
-constexpr int kPivStealEvery = 64;           // tree nodes between looks at the frame queue
-constexpr int kPivStealAfter = 4096;         // nodes of the current root or frame before it may hand over
 
 // ------------------------------------------------------------ binomials
 
@@ -199,10 +199,19 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
     constexpr bool CAN_STEAL = 4 + 3 * MAXW <= kItemWords;
     const bool steal = CAN_STEAL && P.steal;
     int* q = P.qctl;
-    if (steal && (ld_acquire(P.flags) & 2)) return;   // an earlier launch of the call stalled
+    // an earlier launch of the call stalled or was canceled: give up at once
+    if (ld_acquire(P.flags) & (kFlagStalled | kFlagCanceled)) return;
+    if (P.cancel) {
+        int c = 0;
+        if (lane == 0 && cancel_requested(P.cancel)) {
+            atomicOr(P.flags, kFlagCanceled);
+            c = 1;
+        }
+        if (__shfl(c, 0)) return;
+    }
     if (steal && lane == 0) atomicAdd(&q[Q_ROOTING], 1);
-    bool roots_done = false, hungry = false;
-    int cur = -1, chk = 0;                            // root whose S and rows are in LDS
+    bool roots_done = false, hungry = false, canceled = false;
+    int cur = -1, chk = 0, cpoll = 0;                 // root whose S and rows are in LDS
     for (;;) {
         int slot = -1;
         bool from_item = false;
@@ -246,7 +255,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                                                       (static_cast<unsigned long long>(static_cast<unsigned int>(pend)) << 20) ^
                                                       static_cast<unsigned int>(rooting);
                         if (sg != sig) { sig = sg; t_sig = now; }
-                        if ((rooting == 0 && pend == 0) || (ld_acquire(P.flags) & 2)) state = 1;
+                        if ((rooting == 0 && pend == 0) || (ld_acquire(P.flags) & (kFlagStalled | kFlagCanceled))) state = 1;
                         else if (now - t_sig > kStallTicks) state = 2;
                     }
                 }
@@ -257,7 +266,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                 for (int i = 0; i < (1 << backoff); i++) __builtin_amdgcn_s_sleep(127);
             }
             if (idx < 0) {
-                if (state == 2 && lane == 0) atomicOr(P.flags, 2);
+                if (state == 2 && lane == 0) atomicOr(P.flags, kFlagStalled);
                 break;
             }
             if (hungry && lane == 0) atomicAdd(&q[Q_HUNGRY], -1);
@@ -275,7 +284,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             }
             ok = __shfl(ok, 0);
             if (!ok) {
-                if (lane == 0) atomicOr(P.flags, 2);
+                if (lane == 0) atomicOr(P.flags, kFlagStalled);
                 break;
             }
             slot = static_cast<int>(ld_acquire(&it[0]));
@@ -342,7 +351,20 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
         // cost a consumer more (a root extraction) than they save
         int run_nodes = 0;
         for (;;) {
-            if (steal && ++chk == kPivStealEvery && (run_nodes += kPivStealEvery) >= kPivStealAfter) {
+            // cancellation: abandon the tree (the call's result is discarded)
+            if (P.cancel && ++cpoll == kCancelEvery) {
+                cpoll = 0;
+                int c = 0;
+                if (lane == 0 && (cancel_requested(P.cancel) || (ld_acquire(P.flags) & kFlagCanceled))) {
+                    atomicOr(P.flags, kFlagCanceled);
+                    c = 1;
+                }
+                if (__shfl(c, 0)) {
+                    canceled = true;
+                    break;
+                }
+            }
+            if (steal && ++chk >= P.steal_every && (run_nodes += chk) >= P.steal_after) {
                 chk = 0;
                 int want = 0;
                 if (lane == 0) {
@@ -387,7 +409,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                         }
                         ok = __shfl(ok, 0);
                         if (!ok) {
-                            if (lane == 0) atomicOr(P.flags, 2);
+                            if (lane == 0) atomicOr(P.flags, kFlagStalled);
                         } else {
                             unsigned int* f = stk + static_cast<size_t>(fl) * LV;
                             if (lane < MAXW) {
@@ -409,7 +431,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                     }
                 }
             }
-            if (chk == kPivStealEvery) chk = 0;
+            if (chk >= P.steal_every) chk = 0;
             const unsigned long long bal = __ballot(Pr != 0u);
             if (bal == 0ull) {
                 if (level == 0) break;
@@ -459,6 +481,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             }
         }
         wave_sync_lds();
+        if (canceled) break;   // waiting wavefronts leave on the flag
         if (from_item && lane == 0)
             __hip_atomic_fetch_add(&q[Q_PENDING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (from_item) {
@@ -479,7 +502,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             if ((lo | hi) && atomic_add_u128(P.counts + 2 * i, P.counts + 2 * i + 1, lo, hi)) ovf = 1;
         }
     }
-    if (__ballot(ovf != 0) != 0ull && lane == 0) atomicOr(P.flags, 1);
+    if (__ballot(ovf != 0) != 0ull && lane == 0) atomicOr(P.flags, kFlagBigBinom);
     if (STATS && lane == 0) {
         atomicAdd(P.stats, nodes);
         atomicAdd(P.stats + 1, words_done);
@@ -545,6 +568,9 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
     P.qctl = L.w.qctl + kQueueCtlWords * (heavy ? 1 : 0);
     P.qready = L.w.qready + static_cast<size_t>(kQueueCap) * (heavy ? 1 : 0);
     P.qitems = L.w.qitems + static_cast<size_t>(kQueueCap) * kItemWords * (heavy ? 1 : 0);
+    P.steal_every = L.steal_every > 0 ? L.steal_every : kPivStealEvery;
+    P.steal_after = L.steal_after > 0 ? L.steal_after : kPivStealAfter;
+    P.cancel = L.cancel;
     if (!heavy) {
         P.s_cap = kLightCap;
         P.roots = L.w.light;

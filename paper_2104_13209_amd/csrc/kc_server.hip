@@ -94,6 +94,7 @@ struct kc_server {
     std::map<uint64_t, kc::Query*> all;
     uint64_t next_ticket = 1;
     int running = 0;
+    int waiters = 0;                       // threads inside kc_server_wait
     bool stop = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
@@ -176,6 +177,10 @@ extern "C" KC_API int32_t kc_server_create(const kc_dag* dags, int32_t ndags, in
 
 extern "C" KC_API int32_t kc_server_submit(kc_server* sv, int32_t graph, int32_t k, int32_t pivot, uint64_t* ticket) {
     if (!sv || !ticket || graph < 0 || graph >= static_cast<int>(sv->dags.size()) || k < 1) return KC_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stop) return KC_ECANCELED;   // the server is shutting down
+    }
     kc::Query* q = new (std::nothrow) kc::Query();
     if (!q) return KC_ENOMEM;
     q->graph = graph;
@@ -184,6 +189,10 @@ extern "C" KC_API int32_t kc_server_submit(kc_server* sv, int32_t graph, int32_t
     q->need = kc_count_workspace(&sv->dags[graph], k, q->pivot, nullptr);
     q->t_submit = kc::now_s();
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) {
+        delete q;
+        return KC_ECANCELED;
+    }
     q->ticket = sv->next_ticket++;
     *ticket = q->ticket;
     sv->all[q->ticket] = q;
@@ -206,7 +215,9 @@ extern "C" KC_API int32_t kc_server_wait(kc_server* sv, uint64_t ticket, kc_quer
     auto it = sv->all.find(ticket);
     if (it == sv->all.end()) return KC_EINVAL;
     kc::Query* q = it->second;
+    sv->waiters++;
     sv->cv_done.wait(lk, [&] { return q->done; });
+    sv->waiters--;
     res->ticket = q->ticket;
     res->graph = q->graph;
     res->k = q->k;
@@ -219,6 +230,7 @@ extern "C" KC_API int32_t kc_server_wait(kc_server* sv, uint64_t ticket, kc_quer
     res->workspace = q->need;
     sv->all.erase(it);
     delete q;
+    if (sv->stop && sv->waiters == 0) sv->cv_done.notify_all();   // kc_server_destroy may proceed
     return KC_OK;
 }
 
@@ -226,17 +238,27 @@ extern "C" KC_API int32_t kc_server_destroy(kc_server* sv) {
     if (!sv) return KC_EINVAL;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
-        // queries never admitted are dropped
+        // queries never admitted end now with KC_ECANCELED; threads blocked on
+        // them in kc_server_wait wake up and take that result
         for (kc::Query* q : sv->pending) {
-            sv->all.erase(q->ticket);
-            delete q;
+            q->status = KC_ECANCELED;
+            q->t_start = q->t_done = kc::now_s();
+            q->done = true;
         }
         sv->pending.clear();
         sv->stop = true;
     }
     sv->cv_work.notify_all();
+    sv->cv_done.notify_all();
+    // admitted queries finish on their workers
     for (auto& t : sv->workers) t.join();
-    for (auto& kv : sv->all) delete kv.second;
+    {
+        // nothing is freed while a waiter still reads its query
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.wait(lk, [&] { return sv->waiters == 0; });
+        for (auto& kv : sv->all) delete kv.second;
+        sv->all.clear();
+    }
     for (auto s : sv->streams) (void)hipStreamDestroy(s);
     (void)hipFree(sv->arena_mem);
     delete sv->arena;

@@ -26,7 +26,7 @@ def lib():
 def test_header_declares_entry_points():
     names = declared()
     for want in ("kc_orient", "kc_orient_workspace", "kc_count", "kc_count_workspace",
-                 "kc_count_all", "kc_strerror"):
+                 "kc_count_all", "kc_count_noalloc", "kc_strerror"):
         assert want in names
 
 
@@ -56,6 +56,14 @@ def test_host_side_argument_checks(lib):
     # a workspace that is too small is refused
     assert L.kc_count(ctypes.byref(dag), 4, 0, ctypes.byref(res), ctypes.c_void_p(1), 1, None, None) == kc.ENOMEM
     assert L.kc_orient(None, 0, None, None, 0, 1, None) == kc.EINVAL
+    # kc_count_noalloc refuses a DAG whose workspace exceeds its fixed scratch
+    # before touching the device
+    big = kc._Dag(5_000_000, 5_000_000, 64, -1, 0, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                  ctypes.c_void_p(1))
+    assert L.kc_count_workspace(ctypes.byref(big), 4, 0, None) > 64 << 20
+    assert L.kc_count_noalloc(ctypes.byref(big), 4, 0, ctypes.byref(res), None, None) == kc.ENOMEM
+    assert L.kc_count_noalloc(ctypes.byref(big), 1, 0, ctypes.byref(res), None, None) == kc.OK
+    assert (res.lo, res.hi) == (5_000_000, 0)
 
 
 def test_product_path_does_not_use_the_oracle():

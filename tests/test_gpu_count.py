@@ -116,3 +116,20 @@ def test_repeatable(kc, cache):
     g, d = get(cache, kc, "dense_core", kc.ORDER_DEGENERACY)
     vals = {kc.count(d, 5, scheme=s, width=w) for s in (1, 2) for w in (2, 8) for _ in range(2)}
     assert len(vals) == 1
+
+
+@pytest.mark.parametrize("name", sorted(n for n in SMALL if n not in ("k70", "chung_lu")))
+@pytest.mark.parametrize("order", [0, 1])
+def test_count_all_orientation_matches_oracle(kc, cache, name, order):
+    # kc_count_all without pivoting: one orientation traversal per size (K_70
+    # and the Chung-Lu graph, with 1e21 and 8e11 cliques, are left to pivoting)
+    g, d = get(cache, kc, name, order)
+    want, om = oracle.count_all(oracle.orient(g, oracle.DEGENERACY), True, oracle.VC)
+    got, gom = kc.count_all(d, pivot=False, cap=d.d_max + 2)
+    assert gom == om, name
+    assert got[:om + 1] == want[:om + 1], name
+    assert all(c == 0 for c in got[om + 1:])
+    # a cap below omega keeps the exact omega and the counts up to the cap
+    if om > 3:
+        got, gom = kc.count_all(d, pivot=False, cap=3)
+        assert gom == om and got == want[:4]
