@@ -4,7 +4,7 @@
 Workload (one "step"): the power-law graph -- Chung-Lu, n = 1,000,000, mean
 degree 32 (about 16M undirected edges), degree exponent 2.1, expected degrees
 capped at w_max = sqrt(sum of weights) ~ 5657 (Chung-Lu's admissibility bound,
-see the design notes for why the 20k cap is not used at k = 10) -- is
+see the design notes for why the 20k cap is not used at k = 7 and 10) -- is
 validated, oriented by degeneracy order on the GPU, and counted at k = 4, 7 and
 10 without pivoting, edge-centric, through the C ABI.  Inputs are resident in
 HBM before the timed region starts.
@@ -12,11 +12,17 @@ HBM before the timed region starts.
 Output: ONE JSON line on stdout (everything else goes to stderr):
   value      = edges per second of the whole step: m / (step time), where a step
                orients the graph and counts it at every k
-  per_k      = GPU count time (HIP events) and edges/s = m / count time per k
-  roofline   = the dominant traversal kernel against the VALU bound:
-               algorithmic int32 lane-ops = 2 x (bitset words of every expanded
-               tree node) per launch, divided by the kernel's HIP-event duration
-  cpu_baseline = the CPU oracle timed on a bounded root sample of the same graph
+  per_k      = GPU count time (HIP events), edges/s = m / count time and the
+               comparison with the oracle's stored counts, per k
+  roofline   = the dominant traversal launch against the VALU bound:
+               algorithmic int32 lane-ops = 2 x (bitset words of every node of
+               the Fig. 2 tree under that launch's roots), divided by the
+               launch's HIP-event duration
+  cpu_baseline = the CPU oracle timed on a bounded root sample of the same graph,
+               on all host cores and on one
+  literal_wmax20000 = the same graph family with w_max = 20000 at k = 4
+  small, batched, dense_core, served = the other configurations (see their
+               functions), each checked against the oracle where it can be
 """
 import argparse
 import json
@@ -52,6 +58,21 @@ def lane_sources_sha256():
     return h.hexdigest()
 
 
+def golden_counts(name):
+    """{k: c_k} from a stored oracle fixture under tests/golden/ (written by the
+    scripts there, which call only the oracle), or {} when it is missing."""
+    out = {}
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return out
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 3 and parts[0] in ("c", "g"):
+                out[int(parts[1])] = int(parts[2])
+    return out
+
+
 def measured_traffic(k, width_list):
     """HBM bytes of one lane-walk launch (width list, k) from the committed
     FETCH_SIZE / WRITE_SIZE record, or None when there is none or the lane-walk
@@ -69,34 +90,60 @@ def measured_traffic(k, width_list):
     return int(b) if b is not None else None
 
 
+_CPU_DAG = None
+
+
+def _cpu_chunk(task):
+    import oracle
+    k, roots = task
+    return oracle.count(_CPU_DAG, k, False, oracle.EC, roots=roots)
+
+
 def cpu_baseline(g, ks, frac, seed=0):
-    """The oracle (single thread) on a bounded sample: full degeneracy orientation,
-    then every k over a random fraction of the edge roots, scaled to all roots."""
+    """The oracle on a bounded sample of the same workload: full degeneracy
+    orientation (single thread), then every k over a random fraction of the edge
+    roots, scaled to all roots -- once with the sample split over the host's
+    cores (fork pool, started before this process touches the GPU) and once on
+    one core."""
+    global _CPU_DAG
+    import multiprocessing as mp
     import numpy as np
     import oracle
     t0 = time.perf_counter()
     d = oracle.orient(g, oracle.DEGENERACY)
     t_orient = time.perf_counter() - t0
+    _CPU_DAG = d
     rng = np.random.default_rng(seed)
     nsamp = max(1, int(d.m * frac))
     roots = np.sort(rng.choice(d.m, size=nsamp, replace=False))
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    chunks = [roots[i::4 * cores] for i in range(4 * cores)]
     per_k = {}
-    total = t_orient
-    for k in ks:
-        t0 = time.perf_counter()
-        oracle.count(d, k, False, oracle.EC, roots=roots)
-        dt = time.perf_counter() - t0
-        est = dt * d.m / nsamp
-        per_k[str(k)] = {"sample_s": round(dt, 3), "est_count_s": round(est, 2)}
-        total += est
+    total_all, total_one = t_orient, t_orient
+    with mp.get_context("fork").Pool(cores) as pool:
+        for k in ks:
+            t0 = time.perf_counter()
+            c_all = sum(pool.map(_cpu_chunk, [(k, ch) for ch in chunks], chunksize=1))
+            dt_all = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            c_one = oracle.count(d, k, False, oracle.EC, roots=roots)
+            dt_one = time.perf_counter() - t0
+            assert c_all == c_one
+            per_k[str(k)] = {"sample_count": str(c_one), "sample_s_all_cores": round(dt_all, 3),
+                             "sample_s_one_core": round(dt_one, 3),
+                             "est_count_s_all_cores": round(dt_all * d.m / nsamp, 2),
+                             "est_count_s_one_core": round(dt_one * d.m / nsamp, 2)}
+            total_all += dt_all * d.m / nsamp
+            total_one += dt_one * d.m / nsamp
     return {
-        "value": g.m / total,
+        "value": g.m / total_all,
         "unit": "edges/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": "full degeneracy orientation (%.2f s) + counts at k=%s over %d random edge roots "
-                  "(%.2f%% of %d), times scaled to all roots" % (t_orient, ",".join(map(str, ks)), nsamp,
-                                                                100.0 * nsamp / d.m, d.m),
+        "sample": "full degeneracy orientation (%.2f s, one core) + counts at k=%s over %d random edge roots "
+                  "(%.2f%% of %d) split over %d processes, times scaled to all roots"
+                  % (t_orient, ",".join(map(str, ks)), nsamp, 100.0 * nsamp / d.m, d.m, cores),
+        "single_core": {"value": g.m / total_one, "unit": "edges/s", "cores": 1},
         "orient_s": round(t_orient, 3),
         "per_k": per_k,
     }
@@ -150,9 +197,13 @@ def bench_batched(kc, ngraphs, k, reps):
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     mism = sum(1 for x, y in zip(batched, plain) if x != y)
+    fix = golden_counts("batch_counts_k5.txt") if (ngraphs == 10000 and k == 5) else {}
+    matches = all(batched[i] == fix[i] for i in range(b.ngraphs)) if len(fix) == b.ngraphs else None
     return {
-        "workload": "%d graphs, n log-uniform [50, 5000], ER / Chung-Lu(2.3) 50/50, mean degree U[8, 64], "
-                    "seed 4 (%d vertices, %d edges)" % (b.ngraphs, b.n, b.nnz // 2),
+        "workload": "%d graphs, n log-uniform [50, 5000], ER / Chung-Lu(2.3, w_max = n - 1) 50/50, mean degree "
+                    "U[8, 64], seed 4 (%d vertices, %d edges, max degree %d)"
+                    % (b.ngraphs, b.n, b.nnz // 2, bd.max_degree),
+        "matches_oracle": matches,
         "k": k,
         "graphs_per_s": b.ngraphs / wall,
         "ms_per_batch": round(wall * 1e3, 3),
@@ -165,6 +216,44 @@ def bench_batched(kc, ngraphs, k, reps):
         "plan": report,
         "hipgraph": True,
     }
+
+
+def bench_literal(kc, ks, reps):
+    """The power-law graph with expected degrees capped at 20,000 as the
+    configuration states (its saturated core has a few hundred vertices):
+    orientation and counts at the given k, checked against the oracle's stored
+    counts.  k = 7 is outside the time budget of a benchmark step here (see the
+    design notes), so the default is k = 4."""
+    import torch
+    import synth
+    g = synth.config_powerlaw(wmax=20000.0)
+    dev = torch.device("cuda:0")
+    csr = kc.to_device(g, dev)
+    d = kc.orient(csr, kc.ORDER_DEGENERACY)
+    ws = torch.empty(kc.count_workspace_bytes(d, max(ks), False, kc.SCHEME_EC), dtype=torch.uint8, device=dev)
+    fix = golden_counts("powerlaw_wmax20000_counts.txt")
+    out = {"workload": "chung_lu(n=1000000, mean_deg=32, gamma=2.1, wmax=20000, seed=2)", "n": g.n, "m": g.m,
+           "d_max": d.d_max, "degeneracy": d.degeneracy, "order": "degeneracy", "scheme": "EC"}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        kc.orient(csr, kc.ORDER_DEGENERACY, out=d)
+    e1.record()
+    torch.cuda.synchronize()
+    out["orient_ms"] = round(e0.elapsed_time(e1) / reps, 3)
+    for k in ks:
+        c = kc.count(d, k, scheme=kc.SCHEME_EC, ws=ws)
+        ms = []
+        for _ in range(reps):
+            p = kc.Profile()
+            c = kc.count(d, k, scheme=kc.SCHEME_EC, ws=ws, profile=p)
+            ms.append(p.ms_total)
+        t = sum(ms) / len(ms)
+        out[str(k)] = {"count": str(c), "count_ms": round(t, 3), "edges_per_s": g.m / (t / 1e3),
+                       "matches_oracle": (c == fix[k]) if k in fix else None}
+        log("literal: k=%d count %d in %.1f ms" % (k, c, t))
+    return out
 
 
 def bench_small(kc, reps):
@@ -227,16 +316,34 @@ def bench_densecore(kc, reps):
         ws = torch.empty(kc.count_workspace_bytes(d, 0, True, scheme), dtype=torch.uint8, device=dev)
         got, omega = kc.count_all(d, pivot=True, scheme=scheme, ws=ws)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        profs = []
         torch.cuda.synchronize()
         e0.record()
         for _ in range(reps):
-            got, omega = kc.count_all(d, pivot=True, scheme=scheme, ws=ws)
+            p = kc.Profile()
+            got, omega = kc.count_all(d, pivot=True, scheme=scheme, ws=ws, profile=p)
+            profs.append(p)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
+        # pivot roofline: the launch (light |S| <= 64 / heavy roots) with the
+        # most time, its words read per node (|I| + 1 scoring rows + the child's
+        # row) from an untimed stats pass, 2 int32 ops per word
+        sp = kc.Profile()
+        kc.count_all(d, pivot=True, scheme=scheme, ws=ws, profile=sp, collect_stats=True)
+        launch_ms = [sum(p.ms_light for p in profs) / reps, sum(p.ms_heavy for p in profs) / reps]
+        j = 0 if launch_ms[0] >= launch_ms[1] else 1
+        achieved = 2.0 * sp.word_ops[j] / (launch_ms[j] / 1e3) / 1e12
         out[name] = {"count_all_ms": round(ms, 3), "edges_per_s": g.m / (ms / 1e3), "omega": omega,
                      "matches_oracle_counts": (got[:omega + 1] == [fixture.get(k) for k in range(omega + 1)])
-                     if fixture else None}
+                     if fixture else None,
+                     "launch_ms": [round(x, 3) for x in launch_ms],
+                     "roofline": {"bound": "alu", "kernel": "k_piv (%s roots, count-all)" % ("light", "heavy")[j],
+                                  "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                                  "frac": round(achieved / VALU_PEAK_TOPS, 5),
+                                  "work": "2 int32 ops per bitset word: %d tree nodes reading %d words (scoring "
+                                          "|I| + 1 rows per node, W words per child) in %.3f ms"
+                                          % (sp.nodes[j], sp.word_ops[j], launch_ms[j])}}
         log("dense core %s: count-all %.1f ms, omega %d" % (name, ms, omega))
     out["total_cliques"] = str(sum(got[1:]))
     return out
@@ -300,19 +407,28 @@ def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, see
     arr = np.cumsum(gaps) - gaps[0]
     trace = [(float(a), g, k, p) for a, (g, k, p) in zip(arr, qs[nwarm:])]
     out = {}
-    for name, nslots in (("served", slots), ("sequential", 1)):
+    sweep = {}
+    results = {}
+    # the process has 4 hardware queues: slot counts around and above that
+    for name, nslots in (("served", slots), ("sequential", 1), ("slots_2", 2), ("slots_4", 4)):
+        if name.startswith("slots_") and nslots == slots:
+            continue
         with kc.Server(dags, slots=nslots, mem_budget=budget) as sv:
             t0 = time.perf_counter()
             rs = kc.replay_trace(sv, trace)
             span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
         lat = [r.latency * 1e3 for r in rs]
         log("served: %s pass done (%.1f s)" % (name, span))
-        out[name] = {"slots": nslots, "queries_per_s": len(rs) / span, "p50_ms": round(percentile(lat, 50), 3),
-                     "p99_ms": round(percentile(lat, 99), 3), "mean_ms": round(sum(lat) / len(lat), 3),
-                     "refused": sum(1 for r in rs if r.status == kc.ENOMEM),
-                     "errors": sum(1 for r in rs if r.status not in (kc.OK, kc.ENOMEM))}
-        out[name + "_results"] = [(r.status, r.value) for r in rs]
-    same = out.pop("served_results") == out.pop("sequential_results")
+        rec = {"slots": nslots, "queries_per_s": len(rs) / span, "p50_ms": round(percentile(lat, 50), 3),
+               "p99_ms": round(percentile(lat, 99), 3), "mean_ms": round(sum(lat) / len(lat), 3),
+               "refused": sum(1 for r in rs if r.status == kc.ENOMEM),
+               "errors": sum(1 for r in rs if r.status not in (kc.OK, kc.ENOMEM))}
+        sweep[str(nslots)] = rec
+        if not name.startswith("slots_"):
+            out[name] = rec
+        results[nslots] = [(r.status, r.value) for r in rs]
+    same = all(v == results[1] for v in results.values())
+    out["slots_sweep"] = sweep
     # saturation: every query submitted at once (closed loop), throughput only
     for name, nslots in (("served_saturated", slots), ("sequential_saturated", 1)):
         with kc.Server(dags, slots=nslots, mem_budget=budget) as sv:
@@ -345,6 +461,8 @@ def main():
     ap.add_argument("--no-handoff", action="store_true", help="keep subtrees on the wavefront that found them")
     ap.add_argument("--cpu-frac", type=float, default=0.005)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-literal", action="store_true", help="skip the w_max = 20000 leg")
+    ap.add_argument("--literal-ks", default="4", help="k of the w_max = 20000 leg")
     ap.add_argument("--batch-graphs", type=int, default=10000)
     ap.add_argument("--batch-k", type=int, default=5)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -378,6 +496,14 @@ def main():
     t0 = time.perf_counter()
     g = synth.config_powerlaw(n=args.n, wmax=wmax)
     log("graph: n=%d m=%d max_deg=%d (%.1f s)" % (g.n, g.m, int(g.degrees().max()), time.perf_counter() - t0))
+
+    cpu = None
+    if not args.no_cpu:
+        # before this process touches the GPU: the baseline forks worker processes
+        log("cpu baseline (oracle, sampled) ...")
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(g, ks, args.cpu_frac)
+        log("cpu baseline took %.1f s" % (time.perf_counter() - t0))
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -439,6 +565,9 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
 
+    # the oracle's counts of this graph (tests/golden/powerlaw_counts.txt) when
+    # the workload is the default one
+    fix = golden_counts("powerlaw_counts.txt") if (args.n == 1_000_000 and args.wmax <= 0) else {}
     per_k = {}
     phases = []
     for k in ks:
@@ -452,7 +581,8 @@ def main():
                          "light_ms": round(ml, 3), "heavy_ms": round(mh, 3),
                          "width_list_ms": [round(x, 3) for x in mw],
                          "width_list_roots": [int(ps[0].roots_width[j]) for j in range(6)],
-                         "width_list_handoffs": [int(ps[-1].items_width[j]) for j in range(6)]}
+                         "width_list_handoffs": [int(ps[-1].items_width[j]) for j in range(6)],
+                         "matches_oracle": (counts[k] == fix[k]) if k in fix else None}
         phases.append((ms, k, mw))
 
     # dominant kernel launch: at the k that takes longest, the width-list launch
@@ -466,8 +596,18 @@ def main():
     assert c_stats == counts[dom_k]
     dom_j = max(range(6), key=lambda j: dom_mw[j] * float(sp.busy_width[j]))
     dom_ms = dom_mw[dom_j]
-    work_ops = 2.0 * sp.words_width[dom_j]
-    achieved = work_ops / (dom_ms / 1e3) / 1e12
+    # algorithmic work of that launch: the tree of Fig. 2 has one node per
+    # l-clique for l = 3 .. k-1 under each edge root, each an AND + popcount over
+    # the root's W words; untimed stats passes at k' = 3 .. k-1 give, per width
+    # list, the k'-cliques weighted by their root's W (no pruning involved)
+    alg_words = 0
+    for kk in range(3, dom_k):
+        cp = kc.Profile()
+        kc.count(dag, kk, scheme=args.scheme, width=args.width, ws=cws, profile=cp, collect_stats=True,
+                 handoff=not args.no_handoff)
+        alg_words += int(cp.cwords_width[dom_j])
+    achieved = 2.0 * alg_words / (dom_ms / 1e3) / 1e12
+    achieved_expanded = 2.0 * sp.words_width[dom_j] / (dom_ms / 1e3) / 1e12
     roofline = {
         "bound": "alu",
         "kernel": "k_lane<MAXW=%d, %s> (width list %d, k=%d)" % (1 << dom_j, "EC" if args.scheme == 2 else "VC",
@@ -478,10 +618,14 @@ def main():
         "frac": round(achieved / VALU_PEAK_TOPS, 5),
         "traffic": measured_traffic(dom_k, dom_j),
         "traffic_source": "FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy-calibrated) for this launch; profiles/k_lane_powerlaw_k10_hbm_counters.md",
-        "work": "2 int32 ops (AND + popcount) per bitset word per expanded tree node: "
-                "%d nodes with rows of at most %d words (the root's own word count each) = %d words in one "
-                "launch of %.3f ms (HIP events, mean of timed steps)"
-                % (sp.nodes_width[dom_j], 1 << dom_j, sp.words_width[dom_j], dom_ms),
+        "work": "2 int32 ops (AND + popcount) per bitset word per node of the Fig. 2 tree (one node per "
+                "l-clique, l = 3..%d, W = the root's words): %d words in one launch of %.3f ms (HIP events, "
+                "mean of timed steps)" % (dom_k - 1, alg_words, dom_ms),
+        "expanded": {"nodes": int(sp.nodes_width[dom_j]), "words": int(sp.words_width[dom_j]),
+                     "achieved": round(achieved_expanded, 4),
+                     "frac": round(achieved_expanded / VALU_PEAK_TOPS, 5),
+                     "note": "nodes the kernel expands after size pruning (sets too small to complete a "
+                             "k-clique are skipped), leaf level counted as edge counts"},
         "lane_expansions_per_round": round(sp.expand_width[dom_j] / max(1, 64 * sp.iters_width[dom_j]), 4),
         "wavefront_busy_fraction": round(float(sp.busy_width[dom_j]), 4),
         "wavefronts": int(sp.waves_width[dom_j]),
@@ -490,6 +634,11 @@ def main():
         "width_list_wave_iterations": [int(sp.iters_width[j]) for j in range(6)],
         "width_list_expansions": [int(sp.expand_width[j]) for j in range(6)],
     }
+
+    literal = None
+    if not args.no_literal and args.n == 1_000_000:
+        log("literal w_max = 20000 leg ...")
+        literal = bench_literal(kc, [int(x) for x in args.literal_ks.split(",")], args.steps)
 
     batched = None
     if not args.no_batch:
@@ -511,13 +660,6 @@ def main():
         served = bench_served(kc, args.serve_graphs, args.serve_nmin, args.serve_nmax, args.serve_queries,
                               args.serve_warmup, args.serve_slots, args.serve_budget_gb, args.serve_util)
         log("served: %s" % {k: v for k, v in served.items() if k in ("served", "sequential")})
-
-    cpu = None
-    if not args.no_cpu:
-        log("cpu baseline (oracle, sampled) ...")
-        t0 = time.perf_counter()
-        cpu = cpu_baseline(g, ks, args.cpu_frac)
-        log("cpu baseline took %.1f s" % (time.perf_counter() - t0))
 
     res = {
         "metric": "count time + edges/s at k=4,7,10 (non-pivot, edge-centric, degeneracy order)",
@@ -542,6 +684,7 @@ def main():
         "per_k": per_k,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "literal_wmax20000": literal,
         "small": small,
         "batched": batched,
         "dense_core": dense,

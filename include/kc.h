@@ -93,7 +93,8 @@ typedef struct kc_dag {
  * slower variant of the traversal kernels that counts its work: nodes = search
  * tree nodes expanded by the traversal (intersections of a candidate set with
  * one adjacency row), word_ops = sum over those nodes of the root's bitset row
- * length in 32-bit words. */
+ * length in 32-bit words (pivot traversal: plus the |I| + 1 rows of W words
+ * read to choose each node's pivot and form its P'). */
 typedef struct kc_profile {
     float ms_classify;         /* root classification into light / heavy lists */
     float ms_light;            /* traversal kernel over light roots             */
@@ -115,6 +116,10 @@ typedef struct kc_profile {
     int32_t waves_width[6];    /* wavefronts launched                           */
     float busy_width[6];       /* mean wavefront busy time / launch span         */
     int32_t items_width[6];    /* subtrees handed between wavefronts (pair mode) */
+    uint64_t cwords_width[6];  /* stats: k-cliques counted, each weighted by its
+                                  root's bitset row words; summed over k' = 3 ..
+                                  k-1 this is the unpruned Fig. 2 tree's word count
+                                  (one node per k'-clique) */
 } kc_profile;
 
 /* Flags of kc_opts (deep non-pivot counts on the default lane walk):
@@ -226,7 +231,11 @@ KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int
 /* Many independent graphs packed into one CSR (device pointers): graph g owns
  * vertices [voff[g], voff[g+1]) and its rows reference only its own vertices.
  * max_degree bounds every vertex degree (it sizes the radix sort on the host, so
- * no value has to be read back). */
+ * no value has to be read back).  max_graph_edges bounds the undirected edge
+ * count of every graph (0 = unknown): under degree orientation a vertex with t
+ * out-neighbours has t + 1 vertices of degree >= t in its graph, so
+ * t <= sqrt(2 max_graph_edges); the smaller of that and max_degree bounds every
+ * root candidate set. */
 typedef struct kc_batch {
     int32_t ngraphs;
     int32_t n;                 /* total vertices = voff[ngraphs]        */
@@ -235,6 +244,7 @@ typedef struct kc_batch {
     const int32_t* row_ptr;    /* [n+1]                                 */
     const int32_t* col;        /* [nnz]                                 */
     const int32_t* voff;       /* [ngraphs+1]                           */
+    int32_t max_graph_edges;   /* largest m of one graph (0 = unknown)  */
 } kc_batch;
 
 #define KC_BATCH_MAX_BUCKETS 8
@@ -259,7 +269,8 @@ KC_API size_t kc_batch_workspace(const kc_batch* b, int32_t k);
  * replayed.  A per-graph overflow past 2^64 leaves a non-zero hi word (the
  * caller's 64-bit check).  Returns KC_EINVAL for k < 1, bad sizes or a plan
  * with an unknown scheme, KC_ENOMEM for a short workspace, KC_EUNSUPPORTED if
- * max_degree > KC_MAX_DMAX (rows could not be bitset-encoded). */
+ * the out-degree bound min(max_degree, sqrt(2 max_graph_edges)) exceeds
+ * KC_MAX_DMAX (rows could not be bitset-encoded). */
 KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t* counts, void* ws, size_t ws_bytes,
                               const kc_batch_plan* plan, void* stream);
 

@@ -61,7 +61,8 @@ class Profile(ctypes.Structure):
                 ("nodes_width", ctypes.c_uint64 * 6), ("words_width", ctypes.c_uint64 * 6),
                 ("iters_width", ctypes.c_uint64 * 6), ("expand_width", ctypes.c_uint64 * 6),
                 ("waves_width", ctypes.c_int32 * 6),
-                ("busy_width", ctypes.c_float * 6), ("items_width", ctypes.c_int32 * 6)]
+                ("busy_width", ctypes.c_float * 6), ("items_width", ctypes.c_int32 * 6),
+                ("cwords_width", ctypes.c_uint64 * 6)]
 
 
 class _Opts(ctypes.Structure):
@@ -249,14 +250,14 @@ def count(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width:
 
 def count_all_status(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = SCHEME_AUTO,
                      width: int = 0, ws: torch.Tensor | None = None, stream=None,
-                     profile: Profile | None = None, cancel: int = 0):
+                     profile: Profile | None = None, cancel: int = 0, collect_stats: bool = False):
     """(status, [c_0, ..., c_cap], omega) of kc_count_all without raising."""
     L = lib()
     if cap is None:
         cap = d.d_max + 2
     cap = max(int(cap), 2)
     cd = d._c()
-    o = _opts(scheme, width, 0, profile, cancel=cancel)
+    o = _opts(scheme, width, 0, profile, collect_stats, cancel=cancel)
     need = int(L.kc_count_workspace(ctypes.byref(cd), 0, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)
@@ -269,9 +270,10 @@ def count_all_status(d: Dag, pivot: bool = True, cap: int | None = None, scheme:
 
 def count_all(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = SCHEME_AUTO,
               width: int = 0, ws: torch.Tensor | None = None, stream=None,
-              profile: Profile | None = None):
+              profile: Profile | None = None, collect_stats: bool = False):
     """([c_0, ..., c_cap], omega) for every clique size (kc_count_all)."""
-    st, counts, om = count_all_status(d, pivot, cap, scheme, width, ws, stream, profile)
+    st, counts, om = count_all_status(d, pivot, cap, scheme, width, ws, stream, profile,
+                                      collect_stats=collect_stats)
     if st != OK:
         raise KcError(st, "kc_count_all")
     return counts, om
@@ -310,7 +312,7 @@ MAX_BUCKETS = 8
 class _Batch(ctypes.Structure):
     _fields_ = [("ngraphs", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
-                ("voff", ctypes.c_void_p)]
+                ("voff", ctypes.c_void_p), ("max_graph_edges", ctypes.c_int32)]
 
 
 class BatchPlan(ctypes.Structure):
@@ -341,6 +343,7 @@ class BatchDev:
     row_ptr: torch.Tensor
     col: torch.Tensor
     voff: torch.Tensor
+    max_graph_edges: int = 0
 
     @property
     def nnz(self) -> int:
@@ -348,16 +351,19 @@ class BatchDev:
 
     def _c(self) -> _Batch:
         return _Batch(self.ngraphs, self.n, self.nnz, self.max_degree, _ptr(self.row_ptr), _ptr(self.col),
-                      _ptr(self.voff))
+                      _ptr(self.voff), self.max_graph_edges)
 
 
 def batch_to_device(b, device="cuda") -> BatchDev:
     """Copy a host batch (voff, row_ptr, col arrays) to the device."""
-    deg = np.diff(np.asarray(b.row_ptr, dtype=np.int64))
+    rp = np.asarray(b.row_ptr, dtype=np.int64)
+    deg = np.diff(rp)
+    ends = rp[np.asarray(b.voff, dtype=np.int64)]
+    max_m = int(np.diff(ends).max() // 2) if ends.size > 1 else 0
     return BatchDev(int(b.voff.shape[0] - 1), int(b.voff[-1]), int(deg.max()) if deg.size else 0,
                     torch.as_tensor(np.ascontiguousarray(b.row_ptr, np.int32)).to(device),
                     torch.as_tensor(np.ascontiguousarray(b.col, np.int32)).to(device),
-                    torch.as_tensor(np.ascontiguousarray(b.voff, np.int32)).to(device))
+                    torch.as_tensor(np.ascontiguousarray(b.voff, np.int32)).to(device), max_m)
 
 
 def _batch_lib():

@@ -9,6 +9,8 @@
 // kernels pull them from device queues; each wavefront adds the partial counts of
 // a finished root to that root's graph counter.  No host synchronisation, no
 // memset and no device allocation happen inside the call.
+#include <cmath>
+
 #include "kc_count_impl.h"
 
 namespace kc {
@@ -177,8 +179,17 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
                                          const kc_batch_plan* plan, void* stream) {
     if (!b || !counts || k < 1 || b->ngraphs < 1 || b->n < 1 || b->nnz < 0 || (b->nnz & 1)) return KC_EINVAL;
     if (!b->row_ptr || !b->voff || (b->nnz > 0 && !b->col)) return KC_EINVAL;
-    if (b->max_degree < 0) return KC_EINVAL;
-    if (b->max_degree > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    if (b->max_degree < 0 || b->max_graph_edges < 0) return KC_EINVAL;
+    // bound on every out-degree of the degree orientation, hence on |S|
+    int out_bound = b->max_degree;
+    if (b->max_graph_edges > 0) {
+        const long long two_m = 2LL * b->max_graph_edges;
+        long long t = static_cast<long long>(std::sqrt(static_cast<double>(two_m)));
+        while (t * t > two_m) t--;
+        while ((t + 1) * (t + 1) <= two_m) t++;
+        if (t < out_bound) out_bound = static_cast<int>(t);
+    }
+    if (out_bound > KC_MAX_DMAX) return KC_EUNSUPPORTED;
     kc_batch_plan pl{};
     if (plan) {
         pl = *plan;
@@ -215,7 +226,7 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
     if (m == 0) return KC_OK;
 
     int top = 0;
-    while (top < kWidthLists - 1 && (32 << top) < b->max_degree) top++;
+    while (top < kWidthLists - 1 && (32 << top) < out_bound) top++;
     for (int pass = 0; pass < 2; pass++) {
         const bool ec = pass == 1;
         bool used = false;

@@ -652,6 +652,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.stats_ptr = w.acc + 6 + 2 * lst;
             L.iters_ptr = w.acc + 6 + 2 * kWidthLists + 2 * lst;
             L.timing_ptr = w.acc + 6 + 4 * kWidthLists + 3 * lst;
+            L.cwords_ptr = w.acc + kAccCwords + lst;
             L.steal = L.pair && !(o && (o->flags & KC_OPT_NO_HANDOFF));
             L.qctl = w.qctl + kQueueCtlWords * lst;
             L.qready = w.qready + static_cast<size_t>(kQueueCap) * lst;
@@ -781,6 +782,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             prof->iters_width[j] = lane_path && stats ? res[6 + 2 * kWidthLists + 2 * j] : 0;
             prof->items_width[j] = queued ? hq[kQueueCtlWords * j + 1] : 0;   // queue tail
             prof->expand_width[j] = lane_path && stats ? res[7 + 2 * kWidthLists + 2 * j] : 0;
+            prof->cwords_width[j] = lane_path && stats ? res[kAccCwords + j] : 0;
             {
                 const unsigned long long* tm = res + 6 + 4 * kWidthLists + 3 * j;
                 const double span = tm[2] > tm[1] && tm[1] != ~0ull ? static_cast<double>(tm[2] - tm[1]) : 0.0;

@@ -27,7 +27,11 @@ constexpr int kLaneStealAfter = 256;   // lane walk: rounds on the current root 
 constexpr int kPivStealEvery = 64;     // pivot: tree nodes between looks at the frame queue
 constexpr int kPivStealAfter = 4096;   // pivot: nodes of the current root or frame before it may hand over
 constexpr int kCancelEvery = 32;       // wavefront rounds (lane walk) or nodes (pivot) between cancel polls
-constexpr int kAccWords = 9 + 7 * kWidthLists;   // count lo/hi, light/heavy stats, per width list: nodes, words, iterations, expansions, busy, start, end
+// count lo/hi, light/heavy stats, per width list: nodes, words, iterations,
+// expansions, busy, start, end; helper timing (3); per width list: counted
+// cliques weighted by row words
+constexpr int kAccWords = 9 + 8 * kWidthLists;
+constexpr int kAccCwords = 9 + 7 * kWidthLists;
 
 enum CountCtl {
     CC_LIGHT_N = 0,      // light root count
@@ -175,6 +179,7 @@ struct LaneLaunch {
     unsigned long long* stats_ptr;
     unsigned long long* iters_ptr = nullptr;
     unsigned long long* timing_ptr = nullptr;
+    unsigned long long* cwords_ptr = nullptr;   // stats: counted cliques x root row words
     int* grid_out = nullptr;              // receives the launched grid (wavefronts)
     unsigned long long* gacc = nullptr;   // batched: per-graph counters
     const int* gid = nullptr;             // batched: graph of each DAG vertex

@@ -50,6 +50,7 @@ struct LaneParams {
     unsigned long long* stats;      // [nodes, words]
     unsigned long long* iters;      // [traversal loop iterations per wavefront, lane expansions], summed
     unsigned long long* timing;     // [sum of wavefront busy ticks, min start, max end]
+    unsigned long long* cwords;     // stats: sum over counted cliques of the root's bitset words
     unsigned long long* gacc;       // batched: per-graph {lo, hi}; null otherwise
     const int* __restrict__ gid;    // batched: graph of each DAG vertex
     bool steal;                     // pair mode: subtree queue between wavefronts
@@ -189,8 +190,9 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
                                           unsigned int* stk, int* tctr, int* ttot, unsigned long long lt,
                                           unsigned long long& acc, unsigned long long& nodes,
                                           unsigned long long& wsum, unsigned long long& iters,
-                                          unsigned long long& exps) {
+                                          unsigned long long& exps, unsigned long long& cw) {
     constexpr int STRIDE = lane_stride(MW);
+    const unsigned long long acc_in = acc;
     constexpr int SLOT = MW + 1;                    // saved level: R words + p
     const int lane = __lane_id();
     if (fresh) extract_rows<1, false>(s, P.row_ptr, P.col, lane, S, B, STRIDE);
@@ -528,6 +530,8 @@ __device__ __forceinline__ void walk_root(const LaneParams& P, int k, int p0, in
             }
         }
     }
+    // cliques counted by this walk, weighted by the root's row words (stats only)
+    if (STATS) cw += W * (acc - acc_in);
 }
 
 // Extract root `slot` of this list into LDS and walk it with rows of the
@@ -539,17 +543,21 @@ __device__ __forceinline__ void run_root(const LaneParams& P, const int* roots, 
                                          unsigned int* B, int* pre, unsigned int* mbox, unsigned int* stk, int* tctr,
                                          int* ttot, unsigned long long lt, unsigned long long& acc,
                                          unsigned long long& nodes, unsigned long long& wsum,
-                                         unsigned long long& iters, unsigned long long& exps) {
+                                         unsigned long long& iters, unsigned long long& exps,
+                                         unsigned long long& cw) {
     // cached: S and the rows of this root are still in LDS from the previous walk
     if (!cached) extract_set<1, EC>(roots[slot], P.row_ptr, P.col, P.src, __lane_id(), S, &ctl[1]);
     const int s = ctl[1];
     if (EC && k == 3) {
-        if (__lane_id() == 0 && !helping) acc += static_cast<unsigned long long>(s);
+        if (__lane_id() == 0 && !helping) {
+            acc += static_cast<unsigned long long>(s);
+            if (STATS) cw += static_cast<unsigned long long>((s + 31) >> 5) * static_cast<unsigned long long>(s);
+        }
         return;
     }
 #define KC_WALK(MW)                                                                                          \
     walk_root<MW, EC, PAIR, STATS>(P, k, p0, s, slot, helping, item, item_p, !cached, S, B, pre, mbox, stk, tctr, ttot, lt, \
-                                   acc, nodes, wsum, iters, exps)
+                                   acc, nodes, wsum, iters, exps, cw)
     const int Wr = __builtin_amdgcn_readfirstlane((s + 31) >> 5);
     if constexpr (MAXW >= 32) {
         if (Wr > 16) { KC_WALK(32); return; }
@@ -608,7 +616,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
     // an earlier launch of the same call stalled or was canceled: give up at once
     if (P.flags && (ld_acquire(P.flags) & (kFlagStalled | kFlagCanceled))) return;
     if (P.cancel && poll_cancel(P.cancel, P.flags)) return;
-    unsigned long long acc = 0, nodes = 0, wsum = 0, iters = 0, exps = 0, idle = 0;
+    unsigned long long acc = 0, nodes = 0, wsum = 0, iters = 0, exps = 0, idle = 0, cw = 0;
     const unsigned long long t_begin = STATS ? __builtin_amdgcn_s_memrealtime() : 0ull;
     if (steal && lane == 0) atomicAdd(&q[Q_ROOTING], 1);    // in the root phase
     bool helping = steal && P.helper;               // helpers own no roots (and no registry entry)
@@ -655,7 +663,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
         }
         const int graph = P.gacc ? P.gid[EC ? P.src[roots[slot]] : roots[slot]] : 0;
         run_root<MAXW, EC, PAIR, STATS>(P, roots, k, p0, slot, helping, nullptr, 0, false, ctl, S, B, pre, mbox, stk,
-                                        tctr, ttot, lt, acc, nodes, wsum, iters, exps);
+                                        tctr, ttot, lt, acc, nodes, wsum, iters, exps, cw);
         cur = slot;
         if (PAIR && !helping && lane == 0)
             __hip_atomic_store(&P.active[blockIdx.x], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -753,7 +761,7 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
                 slot = static_cast<int>(ibuf[0]);
                 ip = static_cast<int>(ibuf[1]);
                 run_root<MAXW, EC, PAIR, STATS>(P, roots, k, p0, slot, true, ibuf, ip, slot == cur, ctl, S, B, pre,
-                                                mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters, exps);
+                                                mbox, stk, tctr, ttot, lt, acc, nodes, wsum, iters, exps, cw);
                 cur = slot;
                 wave_sync_lds();
                 if (lane == 0) __hip_atomic_fetch_add(&q[Q_PENDING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -785,11 +793,13 @@ __global__ void __launch_bounds__(64) k_lane(LaneParams P) {
         nodes = wave_sum(nodes);
         wsum = wave_sum(wsum);
         exps = wave_sum(exps);
+        cw = wave_sum(cw);
         if (lane == 0) {
             atomicAdd(P.stats, nodes);
             atomicAdd(P.stats + 1, wsum);
             atomicAdd(P.iters, iters);
             atomicAdd(P.iters + 1, exps);
+            if (P.cwords) atomicAdd(P.cwords, cw);
             // busy time of this wavefront (queue waits excluded) and the span of
             // the whole grid (100 MHz constant clock): [sum of busy, min start, max end]
             const unsigned long long t_end = __builtin_amdgcn_s_memrealtime();
@@ -850,6 +860,7 @@ int lane_launch(const LaneLaunch& L, hipStream_t s) {
     P.stats = L.stats_ptr;
     P.iters = L.iters_ptr;
     P.timing = L.timing_ptr;
+    P.cwords = L.cwords_ptr;
     P.gacc = L.gacc;
     P.gid = L.gid;
     P.steal = L.pair && L.steal;

@@ -340,6 +340,8 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             p = static_cast<int>(0xffffu - (best & 0xffffu));
             Po = lane < W ? (I & ~A[p * stride + lane]) : 0u;
             Pr = Po;
+            // scoring reads |I| rows of W words; P' one more
+            if (STATS) words_done += static_cast<unsigned long long>(m + 1) * static_cast<unsigned long long>(W);
             wave_sync_lds();
         };
 

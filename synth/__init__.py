@@ -308,8 +308,8 @@ def batch(ngraphs: int, seed: int = 4, nmin: int = 50, nmax: int = 5000, dmin: f
           dmax: float = 64.0, gamma: float = 2.3) -> Batch:
     """Batched workload: `ngraphs` graphs with vertex counts log-uniform on
     [nmin, nmax], half Erdos-Renyi and half Chung-Lu (degree exponent gamma,
-    weights capped at sqrt(n * mean)), mean degree uniform on [dmin, dmax]
-    capped at n - 1, packed into one CSR."""
+    weights capped at n - 1), mean degree uniform on [dmin, dmax] capped at
+    n - 1, packed into one CSR."""
     lib = _load()
     V = int(lib.synth_batch_vertices(ngraphs, seed, nmin, nmax, dmin, dmax))
     voff = np.zeros(ngraphs + 1, dtype=np.int32)

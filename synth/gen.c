@@ -229,14 +229,13 @@ void synth_batch_params(int32_t g, uint64_t seed, int32_t nmin, int32_t nmax, do
 }
 
 /* Pairs of one batch graph (local ids).  Chung-Lu weights follow a power law
- * w^(-gamma) with the given mean, capped at sqrt(n * mean) (so that
- * w_u w_v <= sum w). */
+ * w^(-gamma) with the given mean, capped at w_max = n - 1 (the largest degree a
+ * simple graph allows); pairs with w_u w_v >= sum w are edges with probability 1. */
 static int64_t batch_graph_pairs(int32_t g, uint64_t seed, int32_t n, int32_t kind, double deg, double gamma,
                                  int32_t** out) {
     uint64_t gs = seed * 1000003ULL + (uint64_t)g * 7919ULL + 17ULL;
     if (kind == 0 || n < 3) return synth_er(n, n > 1 ? deg / (n - 1) : 0.0, gs, out);
-    double wmax = sqrt((double)n * deg);
-    if (wmax > n - 1) wmax = n - 1;
+    double wmax = n - 1;
     /* x_min by bisection on the truncated power-law mean */
     double lo = 1e-6, hi = deg;
     for (int it = 0; it < 200; it++) {

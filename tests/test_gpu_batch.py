@@ -1,10 +1,13 @@
 """Batched per-graph counts (kc_batch_count) against the CPU oracle per graph,
 against per-graph GPU calls, and across HIP-graph replays."""
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from conftest import ROOT
 
 pytestmark = pytest.mark.gpu
 
@@ -68,3 +71,33 @@ def test_batch_graph_replay(kc, small):
         assert bg.counts() == ref, i
         x = torch.randn(1000, device="cuda").sum().item()
         assert x == x
+
+
+def load_batch_fixture():
+    head, counts = {}, []
+    with open(os.path.join(ROOT, "tests", "golden", "batch_counts_k5.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "g":
+                assert int(parts[1]) == len(counts)
+                counts.append(int(parts[2]))
+            else:
+                head[parts[0]] = int(parts[1])
+    return head, counts
+
+
+def test_full_batch_matches_oracle_fixture(kc):
+    # the batched workload at full size (10,000 graphs, ~1.8e8 edges, Chung-Lu
+    # hubs of degree > 1024 whose out-degrees stay within the bitset limit)
+    # against the oracle's per-graph counts, with the autotuner-style plans
+    head, want = load_batch_fixture()
+    b = synth.batch(head["ngraphs"], seed=4)
+    assert (b.n, b.nnz) == (head["n"], head["nnz"])
+    bd = kc.batch_to_device(b)
+    assert bd.max_degree > kc.MAX_DMAX
+    for plan in (None, kc.BatchPlan.make([(200, kc.SCHEME_VC), (1000, kc.SCHEME_EC), (1 << 30, kc.SCHEME_VC)])):
+        got = kc.batch_count(bd, head["k"], plan)
+        bad = [g for g in range(len(want)) if got[g] != want[g]]
+        assert not bad, (plan, bad[:10])
