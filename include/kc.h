@@ -193,6 +193,23 @@ KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t pivot, cons
 KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
                         size_t ws_bytes, const kc_opts* o, void* stream);
 
+/* Per-vertex counts: local[v] = number of k-cliques that contain input vertex v
+ * (DEVICE array of n uint64, indexed by INPUT vertex id, overwritten).  The sum
+ * over v is k times kc_count's result.
+ *   pivot == 0: the graph-orientation traversal (Fig. 2) finds each k-clique
+ *     once, at a node whose path P has k - 1 vertices and whose candidate set is
+ *     I; every vertex of P gains |I| and every member of I gains 1.
+ *   pivot != 0: the pivoting traversal (Fig. 3); a leaf with holds H and pivots
+ *     P stands for C(|P|, k - |H|) k-cliques (Sec. 2.3); every hold gains that
+ *     many and every pivot C(|P| - 1, k - |H| - 1).
+ * k = 1 gives 1 for every vertex, k = 2 the degree.  Uses kc_count_workspace()
+ * bytes of workspace for the same (dag, k, pivot, opts); honours kc_opts.scheme
+ * and cancel.  Returns KC_EOVERFLOW if a vertex's count reaches 2^64.  Deep
+ * counts on skewed graphs are slower than kc_count: every tree stays on the
+ * wavefront that took its root.  Synchronises `stream`. */
+KC_API int32_t kc_count_local(const kc_dag* d, int32_t k, int32_t pivot, uint64_t* local, void* ws,
+                              size_t ws_bytes, const kc_opts* o, void* stream);
+
 /* Size of the fixed device scratch array behind kc_count_noalloc (64 MiB per
  * GPU the library runs on, held until the process ends). */
 #define KC_NOALLOC_SCRATCH_BYTES (64u << 20)
@@ -316,6 +333,13 @@ KC_API int32_t kc_server_destroy(kc_server* s);
 
 /* Static text for a status code. */
 KC_API const char* kc_strerror(int32_t status);
+
+/* Release the library's process-wide pools (the auxiliary streams of deep
+ * non-pivot counts and the timing events of profiled calls, created on first
+ * use).  The library also does this at process exit, before the HIP runtime's
+ * own teardown; calling it earlier is allowed when no call is in flight, and
+ * later calls simply create new pool entries. */
+KC_API void kc_shutdown(void);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@ GPUs" (ICS 2022, arXiv 2104.13209).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -102,6 +103,13 @@ def lib():
         L.kc_count_noalloc.restype = ctypes.c_int32
         L.kc_strerror.argtypes = [ctypes.c_int32]
         L.kc_strerror.restype = ctypes.c_char_p
+        L.kc_count_local.argtypes = [P(_Dag), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_size_t, P(_Opts), ctypes.c_void_p]
+        L.kc_count_local.restype = ctypes.c_int32
+        L.kc_shutdown.argtypes = []
+        L.kc_shutdown.restype = None
+        # release pooled streams and events while the HIP runtime is alive
+        atexit.register(L.kc_shutdown)
         _lib = L
     return _lib
 
@@ -277,6 +285,24 @@ def count_all(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = 
     if st != OK:
         raise KcError(st, "kc_count_all")
     return counts, om
+
+
+def count_local(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
+                ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Per-vertex k-clique counts (kc_count_local): an int64 tensor of n entries
+    indexed by input vertex id, holding the unsigned 64-bit counts."""
+    L = lib()
+    cd = d._c()
+    o = _opts(scheme, 0, 0)
+    need = int(L.kc_count_workspace(ctypes.byref(cd), k, int(bool(pivot)), ctypes.byref(o)))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, d.row_ptr.device)
+    out = torch.empty(max(d.n, 1), dtype=torch.int64, device=d.row_ptr.device)
+    st = L.kc_count_local(ctypes.byref(cd), k, int(bool(pivot)), _ptr(out), _ptr(ws), ws.numel(), ctypes.byref(o),
+                          _stream_handle(stream))
+    if st != OK:
+        raise KcError(st, "kc_count_local")
+    return out[:d.n]
 
 
 def count_noalloc_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, stream=None):

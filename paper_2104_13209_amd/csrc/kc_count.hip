@@ -494,24 +494,6 @@ int launch_heavy(const GoParams& P, int width, int d_max, bool st, hipStream_t s
     return launch_heavy_w<EC, 32>(P, width, s_cap, st, s);
 }
 
-// HIP events for kc_profile, created on first use (one set per process).
-struct ProfileEvents {
-    hipEvent_t ev[4];
-    hipEvent_t wl[2 * kWidthLists];    // start / end of each width-list launch
-    bool ready = false;
-};
-
-int profile_events(ProfileEvents** out) {
-    static ProfileEvents pe;
-    if (!pe.ready) {
-        for (int i = 0; i < 4; i++) KC_CHECK(hipEventCreate(&pe.ev[i]));
-        for (int i = 0; i < 2 * kWidthLists; i++) KC_CHECK(hipEventCreate(&pe.wl[i]));
-        pe.ready = true;
-    }
-    *out = &pe;
-    return KC_OK;
-}
-
 bool valid_dag(const kc_dag* d) {
     if (!d || d->n < 0 || d->m < 0 || d->d_max < 0) return false;
     if (!d->row_ptr) return false;
@@ -536,16 +518,22 @@ int pick_width(const kc_opts* o, int d_max, bool light) {
 
 // Classify roots, run the light and heavy kernels of one traversal, and read
 // the results back.  `pivot_all` selects the pivot kernels (-1: graph
-// orientation, 0: pivot with target k, 1: pivot count-all).
+// orientation, 0: pivot with target k, 1: pivot count-all, 2: pivot per-vertex
+// counts of size k into local_out, which the caller has zeroed).
 int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const CountWs& w, bool ec,
               unsigned long long preload, unsigned long long res[kAccWords], int hctl[CC_WORDS],
-              unsigned long long* counts_out, int counts_len, hipStream_t s) {
+              unsigned long long* counts_out, int counts_len, hipStream_t s,
+              unsigned long long* local_out = nullptr) {
     kc_profile* prof = o ? o->profile : nullptr;
     const bool stats = o && o->collect_stats;
+    // timing events for kc_profile: a set from the per-device pool for this call
+    ProfileGuard pg;
     ProfileEvents* pe = nullptr;
     if (prof) {
-        int st0 = profile_events(&pe);
+        int st0 = profile_acquire(&pg.e);
         if (st0 != KC_OK) return st0;
+        pg.held = true;
+        pe = &pg.e;
         KC_CHECK(hipEventRecord(pe->ev[0], s));
     }
     const int nroots = ec ? d->m : d->n;
@@ -724,6 +712,10 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         PivLaunch L;
         L.k = k;
         L.all = pivot_all == 1;
+        if (pivot_all == 2) {
+            L.local = local_out;
+            L.perm = d->perm;
+        }
         L.ec = ec;
         L.stats = stats;
         L.steal = !(o && (o->flags & KC_OPT_NO_HANDOFF));
@@ -959,6 +951,44 @@ extern "C" KC_API int32_t kc_count_noalloc(const kc_dag* d, int32_t k, int32_t p
         if (st != KC_OK) return st;
     }
     return count_with_ws(d, k, pivot, count, ws, kScratchBytes, &local, static_cast<hipStream_t>(stream));
+}
+
+extern "C" KC_API int32_t kc_count_local(const kc_dag* d, int32_t k, int32_t pivot, uint64_t* local, void* ws,
+                                         size_t ws_bytes, const kc_opts* o, void* stream) {
+    if (!valid_dag(d) || !local || k < 1 || (d->n > 0 && !d->perm)) return KC_EINVAL;
+    if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    size_t need = 0;
+    CountWs w = carve_count(ws, d, pivot != 0, &need);
+    if (!ws || ws_bytes < need) return KC_ENOMEM;
+    if (d->n == 0) return KC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int scheme = pick_scheme(o, k);
+    if (scheme != KC_SCHEME_VC && scheme != KC_SCHEME_EC) return KC_EINVAL;
+    const int* cancel = o ? const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel)) : nullptr;
+    KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
+    int hctl[CC_WORDS];
+    if (pivot && k >= 3 && k <= d->d_max + 1 && d->m > 0) {
+        // the pivoting traversal of Fig. 3 with the per-vertex leaf rule
+        KC_CHECK(hipMemsetAsync(local, 0, sizeof(uint64_t) * static_cast<size_t>(d->n), s));
+        kc_opts lo{};
+        if (o) lo = *o;
+        lo.collect_stats = 0;
+        lo.profile = nullptr;
+        unsigned long long res[kAccWords];
+        const int st = run_count(d, k, 2, &lo, w, scheme == KC_SCHEME_EC, 0ull, res, hctl, nullptr, 0, s,
+                                 reinterpret_cast<unsigned long long*>(local));
+        if (st != KC_OK) return st;
+    } else {
+        const int st = local_orient_launch(d, k, scheme == KC_SCHEME_EC, reinterpret_cast<unsigned long long*>(local),
+                                           w.ctl, cancel, s);
+        if (st != KC_OK) return st;
+        KC_CHECK(hipMemcpyAsync(hctl, w.ctl, sizeof(hctl), hipMemcpyDeviceToHost, s));
+        KC_CHECK(hipStreamSynchronize(s));
+    }
+    if (hctl[CC_FLAGS] & kFlagCanceled) return KC_ECANCELED;
+    if (hctl[CC_FLAGS] & kFlagStalled) return KC_EDEVICE;
+    if (hctl[CC_FLAGS] & (kFlagLocalOverflow | kFlagBigBinom)) return KC_EOVERFLOW;
+    return KC_OK;
 }
 
 extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,

@@ -21,6 +21,7 @@ constexpr int kReadySpins = 1 << 22;                        // wait for a reserv
 constexpr int kFlagBigBinom = 1;    // a binomial beyond 128 bits was used
 constexpr int kFlagStalled = 2;     // a work queue stopped making progress (no valid count)
 constexpr int kFlagCanceled = 4;    // the caller's cancel flag was seen (no valid count)
+constexpr int kFlagLocalOverflow = 8;   // a per-vertex count passed 2^64
 // handoff thresholds (defaults; kc_opts may lower them for tests)
 constexpr int kLaneStealEvery = 16;    // lane walk: wavefront rounds between looks at the subtree queue
 constexpr int kLaneStealAfter = 256;   // lane walk: rounds on the current root or subtree before it may hand over
@@ -139,6 +140,8 @@ struct PivLaunch {
     int steal_every = kPivStealEvery;
     int steal_after = kPivStealAfter;
     const int* cancel = nullptr;   // caller's cancel flag (null: none)
+    unsigned long long* local = nullptr;   // per-vertex counts of size k (input ids); null: totals
+    const int* perm = nullptr;             // DAG id -> input id (local counts)
     int d_max;
     const int* row_ptr;
     const int* col;
@@ -186,6 +189,12 @@ struct LaneLaunch {
 };
 
 int lane_launch(const LaneLaunch& L, hipStream_t s);
+
+// Per-vertex counts by graph orientation (kc_local.hip): zeroes `local` (n
+// entries, input ids) and adds every vertex's k-clique count; ctl is the
+// count workspace's control block (zero at launch).
+int local_orient_launch(const kc_dag* d, int k, bool ec, unsigned long long* local, int* ctl, const int* cancel,
+                        hipStream_t s);
 
 // Capture-safe degree orientation (kc_orient.hip).
 size_t orient_async_workspace(int n, int nnz);

@@ -58,6 +58,23 @@ struct SideGuard {
     }
 };
 
+// Timing events of one profiled call (kc_profile), from a per-device pool.
+struct ProfileEvents {
+    hipEvent_t ev[4] = {};
+    hipEvent_t wl[12] = {};   // start / end of each width-list launch
+    int device = -1;
+};
+int profile_acquire(ProfileEvents* out);   // KC_OK or KC_EDEVICE
+void profile_release(const ProfileEvents& e);
+
+struct ProfileGuard {
+    ProfileEvents e;
+    bool held = false;
+    ~ProfileGuard() {
+        if (held) profile_release(e);
+    }
+};
+
 // ------------------------------------------------------------- device side
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -51,6 +51,8 @@ struct PivParams {
     int* qctl;                               // queue control words (zero at launch)
     int* qready;                             // ring slot sequence words (zero at launch)
     unsigned int* qitems;                    // kItemWords per ring slot
+    const int* __restrict__ perm;            // local counts: DAG id -> input id
+    unsigned long long* local;               // local counts: [n], input ids
     int steal_every;                         // tree nodes between looks at the frame queue
     int steal_after;                         // nodes of the current root or frame before it may hand over
     const int* cancel;                       // caller's cancel flag (null: none)
@@ -137,10 +139,13 @@ __device__ __forceinline__ unsigned int st_load(const unsigned int* p) {
     return *p;
 }
 
-// MAXW: bitset words per row; EC: edge roots; ALL: count every size;
-// GST: stack in global memory; WPB: wavefronts per block (each its own team).
-template <int MAXW, bool EC, bool ALL, bool GST, int WPB, bool STATS>
+// MAXW: bitset words per row; EC: edge roots; MODE: 0 count size k, 1 count
+// every size, 2 per-vertex counts of size k; GST: stack in global memory; WPB:
+// wavefronts per block (each its own team).
+template <int MAXW, bool EC, int MODE, bool GST, int WPB, bool STATS>
 __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
+    constexpr bool ALL = MODE == 1;
+    constexpr bool LOCAL = MODE == 2;
     constexpr int LV = 3 * MAXW + 4;
     extern __shared__ unsigned int lds[];
     const int lane = threadIdx.x & 63;
@@ -148,15 +153,21 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
     const int s_cap = P.s_cap;
     const int stride = b_stride_of(MAXW);
     const int cap = s_cap + 2;                        // largest clique size index
-    const int words = 8 + s_cap + s_cap * stride + (ALL ? 4 * (cap + 1) : 0) +
-                      (GST ? 0 : (s_cap + 2) * LV);
+    const int extra = (ALL ? 4 * (cap + 1) : 0) + (LOCAL ? 4 * s_cap + 2 : 0);
+    const int words = 8 + s_cap + s_cap * stride + extra + (GST ? 0 : (s_cap + 2) * LV);
     unsigned int* base = lds + wv * words;
     int* ctl = reinterpret_cast<int*>(base);
     int* S = reinterpret_cast<int*>(base + 8);        // candidate set, then member list
     unsigned int* A = base + 8 + s_cap;
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(A + s_cap * stride);
+    // local counts: per-root counters of S's members, the path of the current
+    // node (S index of each chosen vertex, top bit set for a pivot) and the
+    // root's S in DAG ids (S itself is reused for member lists)
+    unsigned long long* lcnt = cnt;
+    unsigned int* pathv = A + s_cap * stride + 2 * s_cap;
+    int* S_root = reinterpret_cast<int*>(pathv + s_cap + 2);
     unsigned int* stk = GST ? P.gstack + static_cast<size_t>(blockIdx.x * WPB + wv) * P.slab_words
-                            : A + s_cap * stride + (ALL ? 4 * (cap + 1) : 0);
+                            : A + s_cap * stride + extra;
     const int k = P.k;
     const int N1 = P.binom_n + 1;
     const int nroots = *P.nroots;
@@ -165,11 +176,40 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
     if (ALL)
         for (int i = lane; i < 2 * (cap + 1); i += 64) cnt[i] = 0ull;
     unsigned long long acc_lo = 0, acc_hi = 0, nodes = 0, words_done = 0;
-    int ovf = 0;
+    unsigned long long rootacc = 0;                   // local counts: cliques through the root vertices
+    int ovf = 0, lovf = 0;
 
-    // leaf with nh holds and np pivots
-    auto leaf = [&](int np, int nh) {
-        if (!ALL) {
+    // leaf with nh holds and np pivots; npath vertices below the root(s) on its path
+    auto leaf = [&](int np, int nh, int npath) {
+        if (LOCAL) {
+            // Sec. 2.3: the leaf stands for C(np, k - nh) k-cliques; each hold is
+            // in all of them, each pivot in the C(np - 1, k - nh - 1) that take it
+            if (nh <= k && k - nh <= np) {
+                const size_t ih = static_cast<size_t>(np) * N1 + (k - nh);
+                const unsigned long long ph = P.binom[2 * ih];
+                unsigned long long pp = 0;
+                int big = P.big[ih] | (P.binom[2 * ih + 1] != 0ull);
+                if (np >= 1 && k - nh - 1 >= 0) {
+                    const size_t ip = static_cast<size_t>(np - 1) * N1 + (k - nh - 1);
+                    pp = P.binom[2 * ip];
+                    big |= P.big[ip] | (P.binom[2 * ip + 1] != 0ull);
+                }
+                lovf |= big;
+                if (lane == 0) {
+                    const unsigned long long r = rootacc + ph;
+                    lovf |= r < rootacc;
+                    rootacc = r;
+                }
+                for (int l = lane; l < npath; l += 64) {
+                    const unsigned int e = pathv[l];
+                    const unsigned long long x = (e & 0x80000000u) ? pp : ph;
+                    if (x) {
+                        const unsigned long long old = atomicAdd(&lcnt[e & 0x7fffffffu], x);
+                        lovf |= old + x < old;
+                    }
+                }
+            }
+        } else if (!ALL) {
             if (lane == 0 && nh <= k && nh + np >= k) {
                 const size_t ix = static_cast<size_t>(np) * N1 + (k - nh);
                 ovf |= P.big[ix];
@@ -197,7 +237,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
     // queue: a count of wavefronts in the root phase and a count of published,
     // unfinished frames, both read zero (root phase first) when all work is done.
     constexpr bool CAN_STEAL = 4 + 3 * MAXW <= kItemWords;
-    const bool steal = CAN_STEAL && P.steal;
+    const bool steal = CAN_STEAL && P.steal && !LOCAL;   // local counts keep each tree on one wavefront
     int* q = P.qctl;
     // an earlier launch of the call stalled or was canceled: give up at once
     if (ld_acquire(P.flags) & (kFlagStalled | kFlagCanceled)) return;
@@ -309,9 +349,17 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
         const int s = ctl[1];
         const int W = (s + 31) >> 5;
         if (!from_item && s == 0) {
-            leaf(0, nh_root);
+            leaf(0, nh_root, 0);
             wave_sync_lds();
             continue;
+        }
+        if (LOCAL) {
+            for (int j = lane; j < s; j += 64) {
+                lcnt[j] = 0ull;
+                S_root[j] = S[j];
+            }
+            rootacc = 0;
+            wave_sync_lds();
         }
 
         // choose the pivot of the node with candidates I; sets p, Po, Pr
@@ -456,6 +504,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
             const int np2 = np + (v == p ? 1 : 0);
             const int nh2 = nh + (v != p ? 1 : 0);
             if (!ALL && nh2 > k) continue;                  // stopping criterion: holds <= k
+            if (LOCAL && lane == 0) pathv[level] = static_cast<unsigned int>(v) | (v == p ? 0x80000000u : 0u);
             const unsigned int Ip = lane < W ? (I & A[v * stride + lane] & ~(Po & ~Pr)) : 0u;
             if (STATS) {
                 nodes += 1;
@@ -479,11 +528,33 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                 nh = nh2;
                 enter();
             } else {
-                leaf(np2, nh2);
+                if (LOCAL) wave_sync_lds();   // pathv[level] written by lane 0
+                leaf(np2, nh2, level + 1);
             }
         }
         wave_sync_lds();
         if (canceled) break;   // waiting wavefronts leave on the flag
+        if (LOCAL) {
+            // this root's counts, in input vertex ids
+            for (int j = lane; j < s; j += 64) {
+                const unsigned long long x = lcnt[j];
+                if (x) {
+                    const unsigned long long old = atomicAdd(&P.local[P.perm[S_root[j]]], x);
+                    lovf |= old + x < old;
+                }
+            }
+            if (lane == 0 && rootacc) {
+                const int r = P.roots[slot];
+                const int u = EC ? P.src[r] : r;
+                unsigned long long old = atomicAdd(&P.local[P.perm[u]], rootacc);
+                lovf |= old + rootacc < old;
+                if (EC) {
+                    old = atomicAdd(&P.local[P.perm[P.col[r]]], rootacc);
+                    lovf |= old + rootacc < old;
+                }
+            }
+            wave_sync_lds();
+        }
         if (from_item && lane == 0)
             __hip_atomic_fetch_add(&q[Q_PENDING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (from_item) {
@@ -505,22 +576,26 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
         }
     }
     if (__ballot(ovf != 0) != 0ull && lane == 0) atomicOr(P.flags, kFlagBigBinom);
+    if (LOCAL && __ballot(lovf != 0) != 0ull && lane == 0) atomicOr(P.flags, kFlagLocalOverflow);
     if (STATS && lane == 0) {
         atomicAdd(P.stats, nodes);
         atomicAdd(P.stats + 1, words_done);
     }
 }
 
-template <int MAXW, bool EC, bool ALL, bool GST, int WPB>
+template <int MAXW, bool EC, int MODE, bool GST, int WPB>
 int launch_piv_t(PivParams P, bool stats, int grid_cap_per_cu, hipStream_t s) {
     constexpr int LV = 3 * MAXW + 4;
     const int s_cap = P.s_cap;
     const int cap = s_cap + 2;
-    const int words = 8 + s_cap + s_cap * b_stride_of(MAXW) + (ALL ? 4 * (cap + 1) : 0) +
-                      (GST ? 0 : (s_cap + 2) * LV);
+    const int words = 8 + s_cap + s_cap * b_stride_of(MAXW) + (MODE == 1 ? 4 * (cap + 1) : 0) +
+                      (MODE == 2 ? 4 * s_cap + 2 : 0) + (GST ? 0 : (s_cap + 2) * LV);
     const size_t lds_bytes = static_cast<size_t>(words) * WPB * sizeof(unsigned int);
     if (lds_bytes > 160 * 1024) return KC_EUNSUPPORTED;
-    auto kern = stats ? k_piv<MAXW, EC, ALL, GST, WPB, true> : k_piv<MAXW, EC, ALL, GST, WPB, false>;
+    auto kern = k_piv<MAXW, EC, MODE, GST, WPB, false>;
+    if constexpr (MODE != 2) {   // no stats variant of the local-count kernels
+        if (stats) kern = k_piv<MAXW, EC, MODE, GST, WPB, true>;
+    }
     if (lds_bytes > 64 * 1024)
         KC_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)));
@@ -533,14 +608,19 @@ int launch_piv_t(PivParams P, bool stats, int grid_cap_per_cu, hipStream_t s) {
     return KC_OK;
 }
 
-template <int MAXW, bool GST, int WPB>
-int launch_piv_m(const PivParams& P, bool ec, bool all, bool stats, int cap, hipStream_t s) {
-    if (ec) {
-        return all ? launch_piv_t<MAXW, true, true, GST, WPB>(P, stats, cap, s)
-                   : launch_piv_t<MAXW, true, false, GST, WPB>(P, stats, cap, s);
+template <int MAXW, bool GST, int WPB, bool EC>
+int launch_piv_e(const PivParams& P, int mode, bool stats, int cap, hipStream_t s) {
+    switch (mode) {
+        case 0: return launch_piv_t<MAXW, EC, 0, GST, WPB>(P, stats, cap, s);
+        case 1: return launch_piv_t<MAXW, EC, 1, GST, WPB>(P, stats, cap, s);
+        default: return launch_piv_t<MAXW, EC, 2, GST, WPB>(P, stats, cap, s);
     }
-    return all ? launch_piv_t<MAXW, false, true, GST, WPB>(P, stats, cap, s)
-               : launch_piv_t<MAXW, false, false, GST, WPB>(P, stats, cap, s);
+}
+
+template <int MAXW, bool GST, int WPB>
+int launch_piv_m(const PivParams& P, bool ec, int mode, bool stats, int cap, hipStream_t s) {
+    return ec ? launch_piv_e<MAXW, GST, WPB, true>(P, mode, stats, cap, s)
+              : launch_piv_e<MAXW, GST, WPB, false>(P, mode, stats, cap, s);
 }
 
 }  // namespace
@@ -570,6 +650,9 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
     P.qctl = L.w.qctl + kQueueCtlWords * (heavy ? 1 : 0);
     P.qready = L.w.qready + static_cast<size_t>(kQueueCap) * (heavy ? 1 : 0);
     P.qitems = L.w.qitems + static_cast<size_t>(kQueueCap) * kItemWords * (heavy ? 1 : 0);
+    P.perm = L.perm;
+    P.local = L.local;
+    const int mode = L.local ? 2 : (L.all ? 1 : 0);
     P.steal_every = L.steal_every > 0 ? L.steal_every : kPivStealEvery;
     P.steal_after = L.steal_after > 0 ? L.steal_after : kPivStealAfter;
     P.cancel = L.cancel;
@@ -579,7 +662,7 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
         P.nroots = L.w.ctl + CC_LIGHT_N;
         P.head = L.w.ctl + CC_LIGHT_HEAD;
         P.stats = L.w.acc + 2;
-        return launch_piv_m<2, false, 4>(P, L.ec, L.all, L.stats, 64, s);
+        return launch_piv_m<2, false, 4>(P, L.ec, mode, L.stats, 64, s);
     }
     P.s_cap = s_cap_for(L.d_max);
     P.roots = L.w.heavy;
@@ -588,10 +671,10 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
     P.stats = L.w.acc + 4;
     // the grid cap keeps every wavefront within the global stack slabs carved
     switch (maxw_for(L.d_max)) {
-        case 4: return launch_piv_m<4, true, 4>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
-        case 8: return launch_piv_m<8, true, 4>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
-        case 16: return launch_piv_m<16, true, 1>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
-        default: return launch_piv_m<32, true, 1>(P, L.ec, L.all, L.stats, kPivBlocksPerCU, s);
+        case 4: return launch_piv_m<4, true, 4>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
+        case 8: return launch_piv_m<8, true, 4>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
+        case 16: return launch_piv_m<16, true, 1>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
+        default: return launch_piv_m<32, true, 1>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
     }
 }
 
