@@ -44,7 +44,7 @@ def log(*a):
 
 
 # sources of the lane-walk launches (kernel, launch set-up, shared device code)
-LANE_SOURCES = ("kc_count.hip", "kc_count_impl.h", "kc_extract.h", "kc_internal.h", "kc_lane.hip")
+LANE_SOURCES = ("kc_count.hip", "kc_count_impl.h", "kc_extract.h", "kc_internal.h", "kc_lane.hip", "kc_lane_impl.h")
 
 
 def lane_sources_sha256():
