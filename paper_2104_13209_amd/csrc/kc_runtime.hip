@@ -37,6 +37,10 @@ std::once_flag g_exit_once;
 
 void release_pools() {
     std::lock_guard<std::mutex> lk(g_side_mu);
+    bool any = false;
+    for (auto& kv : g_side_free) any |= !kv.second.empty();
+    for (auto& kv : g_prof_free) any |= !kv.second.empty();
+    if (!any) return;   // nothing to release: no HIP call (also at exit)
     int cur = -1;
     (void)hipGetDevice(&cur);
     for (auto& kv : g_side_free) {
