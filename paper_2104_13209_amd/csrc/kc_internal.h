@@ -162,6 +162,28 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+// Wave-wide maximum of an unsigned 32-bit value with DPP lane moves instead of
+// LDS permutes: swap neighbours and pairs inside each quad, mirror the half rows
+// and rows (every lane then holds its row of 16's maximum), broadcast lane 15
+// into rows 1 and 3 and lane 31 into rows 2 and 3; lane 63 ends with the
+// maximum of all 64 lanes.  Every lane must be active.
+__device__ __forceinline__ unsigned int wave_max_dpp(unsigned int x) {
+    int v = static_cast<int>(x);
+#define KC_DPP_MAX(ctrl, rows)                                                                    \
+    {                                                                                             \
+        const unsigned int t = static_cast<unsigned int>(__builtin_amdgcn_update_dpp(v, v, ctrl, rows, 0xf, false)); \
+        v = static_cast<int>(t > static_cast<unsigned int>(v) ? t : static_cast<unsigned int>(v)); \
+    }
+    KC_DPP_MAX(0xB1, 0xf)    // quad_perm [1, 0, 3, 2]
+    KC_DPP_MAX(0x4E, 0xf)    // quad_perm [2, 3, 0, 1]
+    KC_DPP_MAX(0x141, 0xf)   // row_half_mirror
+    KC_DPP_MAX(0x140, 0xf)   // row_mirror
+    KC_DPP_MAX(0x142, 0xa)   // row_bcast:15 into rows 1 and 3
+    KC_DPP_MAX(0x143, 0xc)   // row_bcast:31 into rows 2 and 3
+#undef KC_DPP_MAX
+    return static_cast<unsigned int>(__builtin_amdgcn_readlane(v, 63));
+}
+
 template <class T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll

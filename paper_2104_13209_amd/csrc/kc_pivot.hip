@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                     best = key > best ? key : best;
                 }
             }
-            best = wave_max(best);
+            best = wave_max_dpp(best);
             p = static_cast<int>(0xffffu - (best & 0xffffu));
             Po = lane < W ? (I & ~A[p * stride + lane]) : 0u;
             Pr = Po;
@@ -671,7 +671,10 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
     P.stats = L.w.acc + 4;
     // the grid cap keeps every wavefront within the global stack slabs carved
     switch (maxw_for(L.d_max)) {
-        case 4: return launch_piv_m<4, true, 4>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
+        case 4:
+            // rows of at most 4 words: the frames fit in LDS beside the rows
+            // (about 13.5 KB per wavefront at |S| = 128), so the stack stays on chip
+            return launch_piv_m<4, false, 4>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
         case 8: return launch_piv_m<8, true, 4>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
         case 16: return launch_piv_m<16, true, 1>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
         default: return launch_piv_m<32, true, 1>(P, L.ec, mode, L.stats, kPivBlocksPerCU, s);
