@@ -635,6 +635,17 @@ def main():
         "width_list_expansions": [int(sp.expand_width[j]) for j in range(6)],
     }
 
+    # ablation (Sec. 4.3): the same counts without binary encoding, at small k
+    ablation = {"workload": "the timed graph, edge roots", "note": "KC_OPT_NO_BITSETS: sorted candidate lists, "
+                "binary-search intersections in the oriented CSR, one wavefront per root"}
+    for k in (4, 5):
+        pb, pl = kc.Profile(), kc.Profile()
+        cb = kc.count(dag, k, scheme=kc.SCHEME_EC, ws=cws, profile=pb)
+        cl = kc.count(dag, k, scheme=kc.SCHEME_EC, ws=cws, profile=pl, bitsets=False)
+        ablation[str(k)] = {"bitsets_ms": round(pb.ms_total, 3), "lists_ms": round(pl.ms_total, 3),
+                            "bitset_speedup": round(pl.ms_total / pb.ms_total, 2), "same_count": cb == cl}
+    log("ablation: %s" % ablation)
+
     literal = None
     if not args.no_literal and args.n == 1_000_000:
         log("literal w_max = 20000 leg ...")
@@ -685,6 +696,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "literal_wmax20000": literal,
+        "ablation_no_bitsets": ablation,
         "small": small,
         "batched": batched,
         "dense_core": dense,

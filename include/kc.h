@@ -122,12 +122,18 @@ typedef struct kc_profile {
                                   (one node per k'-clique) */
 } kc_profile;
 
-/* Flags of kc_opts (deep non-pivot counts on the default lane walk):
+/* Flags of kc_opts:
  * KC_OPT_NO_HANDOFF      wavefronts never hand subtrees to idle wavefronts;
  * KC_OPT_SINGLE_STREAM   every launch stays on the caller's stream (no side
  *                        stream for the widest root list, no helper launch):
- *                        for callers that already run many counts at once. */
-enum { KC_OPT_NO_HANDOFF = 1, KC_OPT_SINGLE_STREAM = 2 };
+ *                        for callers that already run many counts at once;
+ * KC_OPT_NO_BITSETS      non-pivot counts without binary encoding (the
+ *                        ablation of Sec. 4.3): candidate sets are sorted vertex
+ *                        lists and each intersection binary-searches the members
+ *                        in the branch vertex's out-list, one wavefront per root.
+ *                        Same counts; KC_EUNSUPPORTED when (k - 2) lists of
+ *                        d_max entries do not fit one wavefront's LDS. */
+enum { KC_OPT_NO_HANDOFF = 1, KC_OPT_SINGLE_STREAM = 2, KC_OPT_NO_BITSETS = 4 };
 
 /* Tuning options; NULL means defaults.  scheme: KC_SCHEME_*; width: lanes per
  * sub-wavefront group (1, 2, 4, 8, 16, 32 or 64; 0 = auto) (Sec. 3.5).

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libkc.so")
 
 ORDER_DEGREE, ORDER_DEGENERACY = 0, 1
 SCHEME_AUTO, SCHEME_VC, SCHEME_EC = 0, 1, 2
-OPT_NO_HANDOFF, OPT_SINGLE_STREAM = 1, 2
+OPT_NO_HANDOFF, OPT_SINGLE_STREAM, OPT_NO_BITSETS = 1, 2, 4
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ECANCELED, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MAX_DMAX = 1024
 
@@ -205,8 +205,9 @@ def orient(g: Csr, order: int = ORDER_DEGREE, validate: bool = True, ws: torch.T
 
 def _opts(scheme: int, width: int, test_preload: int, profile: Profile | None = None,
           collect_stats: bool = False, handoff: bool = True, single_stream: bool = False,
-          cancel: int = 0, handoff_after: int = 0, handoff_every: int = 0) -> _Opts:
-    flags = (0 if handoff else OPT_NO_HANDOFF) | (OPT_SINGLE_STREAM if single_stream else 0)
+          cancel: int = 0, handoff_after: int = 0, handoff_every: int = 0, bitsets: bool = True) -> _Opts:
+    flags = ((0 if handoff else OPT_NO_HANDOFF) | (OPT_SINGLE_STREAM if single_stream else 0) |
+             (0 if bitsets else OPT_NO_BITSETS))
     o = _Opts(scheme, width, int(bool(collect_stats)), flags, test_preload, None,
               ctypes.c_void_p(cancel or None), handoff_after, handoff_every)
     if profile is not None:
@@ -224,14 +225,14 @@ def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
                  ws: torch.Tensor | None = None, test_preload: int = 0, stream=None,
                  profile: Profile | None = None, collect_stats: bool = False, handoff: bool = True,
                  single_stream: bool = False, cancel: int = 0, handoff_after: int = 0,
-                 handoff_every: int = 0):
+                 handoff_every: int = 0, bitsets: bool = True):
     """(status, count) of kc_count without raising.  cancel: address of a
     device-readable int32 (device memory or mapped host memory) that stops the
     count with ECANCELED once it holds a non-zero value."""
     L = lib()
     cd = d._c()
     o = _opts(scheme, width, test_preload, profile, collect_stats, handoff, single_stream, cancel,
-              handoff_after, handoff_every)
+              handoff_after, handoff_every, bitsets)
     need = int(L.kc_count_workspace(ctypes.byref(cd), k, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)
@@ -244,13 +245,14 @@ def count_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
 def count(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width: int = 0,
           ws: torch.Tensor | None = None, stream=None, profile: Profile | None = None,
           collect_stats: bool = False, handoff: bool = True, single_stream: bool = False,
-          handoff_after: int = 0, handoff_every: int = 0) -> int:
+          handoff_after: int = 0, handoff_every: int = 0, bitsets: bool = True) -> int:
     """Number of k-cliques (kc_count); exact Python int.  handoff=False keeps
     every subtree on the wavefront that found it; single_stream=True keeps every
     launch on `stream` (KC_OPT_* flags); handoff_after / handoff_every lower the
-    handoff thresholds (0 = defaults)."""
+    handoff thresholds (0 = defaults); bitsets=False runs the list-intersection
+    ablation (KC_OPT_NO_BITSETS)."""
     st, val = count_status(d, k, pivot, scheme, width, ws, 0, stream, profile, collect_stats, handoff,
-                           single_stream, 0, handoff_after, handoff_every)
+                           single_stream, 0, handoff_after, handoff_every, bitsets)
     if st != OK:
         raise KcError(st, "kc_count")
     return val

@@ -556,7 +556,8 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     int cblocks = div_up(nroots, kBlock);
     if (cblocks > device_cus() * 8) cblocks = device_cus() * 8;
     if (cblocks < 1) cblocks = 1;
-    bool lane_path = pivot_all < 0 && (o ? o->width : 0) <= 1;
+    const bool lists = pivot_all < 0 && o && (o->flags & KC_OPT_NO_BITSETS);
+    bool lane_path = pivot_all < 0 && !lists && (o ? o->width : 0) <= 1;
     if (lane_path) {
         // the widest list must fit one wavefront's LDS; otherwise use the group walk
         int top = 0;
@@ -676,6 +677,11 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
                 KC_CHECK(hipEventRecord(pe->wl[2 * lst], s));
                 KC_CHECK(hipEventRecord(pe->wl[2 * lst + 1], s));
             }
+    } else if (lists) {
+        st = lists_launch(d, k, ec, w, o->cancel ? const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel))
+                                                 : nullptr, s);
+        if (st != KC_OK) return st;
+        if (prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
     } else if (pivot_all < 0) {
         GoParams P;
         P.n = d->n;

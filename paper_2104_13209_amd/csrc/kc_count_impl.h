@@ -190,6 +190,10 @@ struct LaneLaunch {
 
 int lane_launch(const LaneLaunch& L, hipStream_t s);
 
+// Graph orientation over sorted candidate lists and binary-search
+// intersections instead of bitsets (kc_lists.hip; KC_OPT_NO_BITSETS).
+int lists_launch(const kc_dag* d, int k, bool ec, const CountWs& w, const int* cancel, hipStream_t s);
+
 // Per-vertex counts by graph orientation (kc_local.hip): zeroes `local` (n
 // entries, input ids) and adds every vertex's k-clique count; ctl is the
 // count workspace's control block (zero at launch).

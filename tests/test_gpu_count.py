@@ -133,3 +133,16 @@ def test_count_all_orientation_matches_oracle(kc, cache, name, order):
     if om > 3:
         got, gom = kc.count_all(d, pivot=False, cap=3)
         assert gom == om and got == want[:4]
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_list_intersection_ablation_matches_oracle(kc, cache, name, scheme):
+    # KC_OPT_NO_BITSETS: sorted lists and binary-search intersections instead of
+    # bitset rows (the paper's non-binary-encoded variant)
+    for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY):
+        g, d = get(cache, kc, name, order)
+        kmax = min(d.d_max + 2, 8 if name != "k70" else 5)
+        want = oracle_counts(g, range(3, kmax + 1))
+        for k in range(3, kmax + 1):
+            assert kc.count(d, k, pivot=False, scheme=scheme, bitsets=False) == want[k], (name, order, scheme, k)

@@ -60,3 +60,11 @@ def test_powerlaw_literal_wmax(kc):
     for k in sorted(want):
         print("powerlaw w_max 20000: k=%d" % k, flush=True)
         assert kc.count(d, k, pivot=False, scheme=kc.SCHEME_EC) == want[k], k
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_powerlaw_list_intersection_ablation(kc, variant, k):
+    # the non-bitset traversal (KC_OPT_NO_BITSETS) at full size
+    d, want = variant
+    print("powerlaw w_max 5657: k=%d without bitsets" % k, flush=True)
+    assert kc.count(d, k, pivot=False, scheme=kc.SCHEME_EC, bitsets=False) == want[k]
