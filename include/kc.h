@@ -7,8 +7,10 @@
  * whose vertices are pairwise adjacent.
  *
  * Pipeline behind this header:
- *   kc_orient   orient G into a DAG by degree or degeneracy order (Sec. 3.1),
+ *   kc_orient   orient G into a DAG by degree, degeneracy or approximate
+ *               degeneracy order (Sec. 3.1),
  *               filter edges and rebuild the CSR by histogram + exclusive scan;
+ *   kc_list     list the k-cliques themselves (the orientation traversal);
  *   kc_count    traverse one search tree per root vertex (vertex-centric) or root
  *               edge (edge-centric) (Sec. 3.2) over the root's induced sub-graph
  *               encoded as bitsets (Sec. 2.4, 3.4), without pivoting (Fig. 2) or
@@ -51,13 +53,18 @@ typedef enum kc_status {
     KC_EUNSUPPORTED = -6   /* graph exceeds a documented limit of this build     */
 } kc_status;
 
-enum { KC_ORDER_DEGREE = 0, KC_ORDER_DEGENERACY = 1 };
+enum { KC_ORDER_DEGREE = 0, KC_ORDER_DEGENERACY = 1, KC_ORDER_APPROX_DEGENERACY = 2 };
 enum { KC_SCHEME_AUTO = 0, KC_SCHEME_VC = 1, KC_SCHEME_EC = 2 };
 
-/* Largest root candidate set (out-degree) the traversal kernels support: the
- * root's bitset rows live in LDS, s x ceil(s/32) words.  kc_count returns
- * KC_EUNSUPPORTED when the DAG's d_max exceeds it. */
+/* Largest out-degree whose roots keep their bitset rows on chip (LDS,
+ * s x ceil(s/32) words).  Roots whose first vertex has a longer out-row ("wide
+ * roots") are counted by kc_count and kc_count_all from rows in a global-memory
+ * slab per wavefront (Sec. 3.3, 3.6 keep sub-graphs and stacks in pre-allocated
+ * global memory), up to KC_MAX_DMAX_WIDE.  kc_count_local, the list-
+ * intersection ablation and kc_batch_count stay within KC_MAX_DMAX and return
+ * KC_EUNSUPPORTED beyond it. */
 #define KC_MAX_DMAX 1024
+#define KC_MAX_DMAX_WIDE 8192
 
 /* Undirected input graph (Sec. 3.1 CSR): row_ptr[n+1], col[nnz], each row
  * strictly increasing, no self-loops, symmetric (u in row v iff v in row u).
@@ -170,8 +177,14 @@ typedef struct kc_opts {
 KC_API size_t kc_orient_workspace(int32_t n, int32_t nnz, int32_t order);
 
 /* Orient g (Sec. 3.1).  order: KC_ORDER_DEGREE (edge u->v iff (deg u, u) <
- * (deg v, v)) or KC_ORDER_DEGENERACY (k-core removal order from GPU peeling in
- * level-synchronous rounds; ties inside a round by id).  Fills *out (device
+ * (deg v, v)), KC_ORDER_DEGENERACY (k-core removal order from GPU peeling in
+ * level-synchronous rounds; ties inside a round by id) or
+ * KC_ORDER_APPROX_DEGENERACY (a relaxation of k-core, among the criteria of
+ * Sec. 2: in rounds, every remaining vertex whose current degree is at most 1.5
+ * times the remaining graph's average degree, i.e. 2 deg L <= 3 D for L
+ * vertices of degree sum D, leaves at once; order by (round, id); fewer rounds
+ * than exact peeling, out-degrees at most 3 times the degeneracy;
+ * dag->degeneracy is -1 as for degree order).  Fills *out (device
  * arrays must hold n+1, m, m and n int32 with m = nnz/2) and its host fields;
  * synchronises `stream`.  validate != 0 first checks that g is a sorted simple
  * symmetric CSR and returns KC_EINVAL if not; with validate == 0 a malformed
@@ -195,7 +208,8 @@ KC_API size_t kc_count_workspace(const kc_dag* d, int32_t k, int32_t pivot, cons
  * is set; wavefronts hand work to idle ones through the workspace's queues unless
  * KC_OPT_NO_HANDOFF is set.  KC_EDEVICE is returned when such a queue stops making
  * progress for 20 s (no count is valid then).  One workspace serves one call at a
- * time. */
+ * time.  Wide roots (see KC_MAX_DMAX) run after the others, one wavefront each;
+ * KC_EUNSUPPORTED when d_max exceeds KC_MAX_DMAX_WIDE. */
 KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, void* ws,
                         size_t ws_bytes, const kc_opts* o, void* stream);
 
@@ -212,9 +226,25 @@ KC_API int32_t kc_count(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* coun
  * bytes of workspace for the same (dag, k, pivot, opts); honours kc_opts.scheme
  * and cancel.  Returns KC_EOVERFLOW if a vertex's count reaches 2^64.  Deep
  * counts on skewed graphs are slower than kc_count: every tree stays on the
- * wavefront that took its root.  Synchronises `stream`. */
+ * wavefront that took its root.  KC_EUNSUPPORTED when d_max exceeds KC_MAX_DMAX.
+ * Synchronises `stream`. */
 KC_API int32_t kc_count_local(const kc_dag* d, int32_t k, int32_t pivot, uint64_t* local, void* ws,
                               size_t ws_bytes, const kc_opts* o, void* stream);
+
+/* k-clique listing (the orientation traversal of Fig. 2 with a listing leaf:
+ * a node whose path P has k - 1 vertices and candidate set I stands for the
+ * cliques P + {w}, w in I).  Writes up to `cap` cliques into the DEVICE array
+ * cliques[cap * k], one row of k INPUT vertex ids per clique in ascending
+ * orientation rank (the clique's lowest-ranked vertex first), and the number of
+ * k-cliques into *total (host).  When *total > cap, the first cap rows hold cap
+ * of them (which ones is unspecified: rows are reserved by concurrent
+ * wavefronts); otherwise the first *total rows hold every k-clique once, in an
+ * unspecified row order.  k = 1 lists the vertices, k = 2 the edges.  Uses
+ * kc_count_workspace(d, k, 0, o) bytes; honours kc_opts.scheme and cancel.
+ * KC_EINVAL for k < 1, cap < 0 or a NULL array with cap > 0; KC_EUNSUPPORTED when
+ * d_max exceeds KC_MAX_DMAX.  Synchronises `stream`. */
+KC_API int32_t kc_list(const kc_dag* d, int32_t k, int32_t* cliques, int64_t cap, uint64_t* total, void* ws,
+                       size_t ws_bytes, const kc_opts* o, void* stream);
 
 /* Size of the fixed device scratch array behind kc_count_noalloc (64 MiB per
  * GPU the library runs on, held until the process ends). */
@@ -243,8 +273,9 @@ KC_API int32_t kc_count_noalloc(const kc_dag* d, int32_t k, int32_t pivot, kc_u1
  * traversal for every size (Sec. 2.3).  pivot == 0 runs the graph-orientation
  * traversal (Fig. 2) once per size, k = 3, 4, ..., until a size has no clique
  * (at most d_max + 1), so its cost is one kc_count per size up to omega + 1
- * whatever cap is.  Returns KC_EINVAL if cap < 2 and KC_EOVERFLOW if a count
- * needs more than 128 bits.  Synchronises `stream`. */
+ * whatever cap is.  Returns KC_EINVAL if cap < 2, KC_EOVERFLOW if a count
+ * needs more than 128 bits and KC_EUNSUPPORTED when d_max exceeds
+ * KC_MAX_DMAX_WIDE.  Synchronises `stream`. */
 KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,
                             int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
                             void* stream);

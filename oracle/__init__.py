@@ -24,7 +24,7 @@ _SRCS = [os.path.join(_HERE, "kc_oracle.c"), os.path.join(_HERE, "kc_brute.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-DEGREE, DEGENERACY = 0, 1
+DEGREE, DEGENERACY, APPROX_DEGENERACY = 0, 1, 2
 VC, EC = 1, 2
 OK, EINVAL, ENOMEM, EOVERFLOW = 0, -1, -2, -3
 

@@ -29,6 +29,13 @@
  *   R4  Degree order: edge u->v iff (deg u, u) < (deg v, v).
  *   R5  Degeneracy order: repeatedly remove a vertex of minimum current degree,
  *       smallest id first on ties (Matula-Beck); edge u->v iff u is removed first.
+ *   R8  Approximate degeneracy order (a relaxation of k-core, one of the
+ *       orientation criteria of Sec. 2; the rule of ARB-COUNT's approximate
+ *       peeling with eps = 1/2): in rounds r = 0, 1, ..., with L vertices left
+ *       of total current degree D, every remaining vertex whose degree is at
+ *       most 1.5 D / L (2 deg L <= 3 D, exact in integers) leaves in round r;
+ *       then the remaining neighbours of the leavers lose one degree each.  The
+ *       order is by (round, id).
  *   R6  k = 1 gives n, k = 2 gives m (outside the pseudocode); counts[0] = 1 is
  *       the empty clique.
  *   R7  Counts are unsigned 128-bit; any carry out of bit 127 sets an overflow flag.
@@ -44,7 +51,7 @@
 typedef unsigned __int128 u128;
 
 enum { KCO_OK = 0, KCO_EINVAL = -1, KCO_ENOMEM = -2, KCO_EOVERFLOW = -3 };
-enum { KCO_DEGREE = 0, KCO_DEGENERACY = 1 };
+enum { KCO_DEGREE = 0, KCO_DEGENERACY = 1, KCO_APPROX_DEGENERACY = 2 };
 enum { KCO_VC = 1, KCO_EC = 2 };
 
 /* ------------------------------------------------------------------ input */
@@ -116,11 +123,12 @@ static int64_t heap_pop(heap64* h) {
  * (R4 / R5); the DAG keeps edge u->v iff rank[u] < rank[v].  Out-lists are in
  * vertex id order.  out_ptr has n+1 entries, out_col m = nnz/2 entries.
  * *degeneracy receives the largest current degree seen at a removal (degeneracy
- * order) or -1 (degree order). */
+ * order) or -1 (degree and approximate degeneracy order). */
 int kco_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int order,
                int32_t* out_ptr, int32_t* out_col, int32_t* rank,
                int32_t* d_max, int32_t* degeneracy) {
-    if (n < 0 || (order != KCO_DEGREE && order != KCO_DEGENERACY)) return KCO_EINVAL;
+    if (n < 0 || (order != KCO_DEGREE && order != KCO_DEGENERACY && order != KCO_APPROX_DEGENERACY))
+        return KCO_EINVAL;
     int32_t* ids = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
     int32_t* deg = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
     if (!ids || !deg) { free(ids); free(deg); return KCO_ENOMEM; }
@@ -130,6 +138,26 @@ int kco_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int order,
         for (int32_t v = 0; v < n; v++) ids[v] = v;
         g_deg_for_sort = deg;
         qsort(ids, (size_t)n, sizeof(int32_t), cmp_degree_id);
+    } else if (order == KCO_APPROX_DEGENERACY) {
+        /* R8: whole rounds of low-degree vertices, in id order within a round */
+        int32_t* round = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+        if (!round) { free(ids); free(deg); return KCO_ENOMEM; }
+        for (int32_t v = 0; v < n; v++) round[v] = -1;
+        int32_t removed = 0;
+        for (int32_t r = 0; removed < n; r++) {
+            int64_t L = 0, D = 0;
+            for (int32_t v = 0; v < n; v++)
+                if (round[v] < 0) { L++; D += deg[v]; }
+            int32_t first = removed;
+            for (int32_t v = 0; v < n; v++)
+                if (round[v] < 0 && 2 * (int64_t)deg[v] * L <= 3 * D) { round[v] = r; ids[removed++] = v; }
+            for (int32_t i = first; i < removed; i++) {
+                int32_t v = ids[i];
+                for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+                    if (round[col[e]] < 0) deg[col[e]]--;
+            }
+        }
+        free(round);
     } else {
         /* Matula-Beck peel: pop the (current degree, id) minimum; skip stale
          * heap entries; decrement the degrees of still-present neighbours. */

@@ -23,11 +23,12 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libkc.so")
 
-ORDER_DEGREE, ORDER_DEGENERACY = 0, 1
+ORDER_DEGREE, ORDER_DEGENERACY, ORDER_APPROX_DEGENERACY = 0, 1, 2
 SCHEME_AUTO, SCHEME_VC, SCHEME_EC = 0, 1, 2
 OPT_NO_HANDOFF, OPT_SINGLE_STREAM, OPT_NO_BITSETS = 1, 2, 4
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ECANCELED, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-MAX_DMAX = 1024
+MAX_DMAX = 1024          # out-degree whose roots keep their bitset rows on chip
+MAX_DMAX_WIDE = 8192     # out-degree limit of kc_count / kc_count_all (wide roots in global memory)
 
 
 class KcError(RuntimeError):
@@ -106,6 +107,9 @@ def lib():
         L.kc_count_local.argtypes = [P(_Dag), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_size_t, P(_Opts), ctypes.c_void_p]
         L.kc_count_local.restype = ctypes.c_int32
+        L.kc_list.argtypes = [P(_Dag), ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, P(ctypes.c_uint64),
+                              ctypes.c_void_p, ctypes.c_size_t, P(_Opts), ctypes.c_void_p]
+        L.kc_list.restype = ctypes.c_int32
         L.kc_shutdown.argtypes = []
         L.kc_shutdown.restype = None
         # release pooled streams and events while the HIP runtime is alive
@@ -305,6 +309,37 @@ def count_local(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO,
     if st != OK:
         raise KcError(st, "kc_count_local")
     return out[:d.n]
+
+
+def list_cliques_status(d: Dag, k: int, cap: int, scheme: int = SCHEME_AUTO, ws: torch.Tensor | None = None,
+                        stream=None, cancel: int = 0):
+    """(status, total, rows) of kc_list without raising: rows is an int32 tensor
+    of min(total, cap) cliques (k input ids each, ascending orientation rank)."""
+    L = lib()
+    cd = d._c()
+    o = _opts(scheme, 0, 0, cancel=cancel)
+    need = int(L.kc_count_workspace(ctypes.byref(cd), k, 0, ctypes.byref(o)))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, d.row_ptr.device)
+    cap = max(int(cap), 0)
+    out = torch.empty((max(cap, 1), max(k, 1)), dtype=torch.int32, device=d.row_ptr.device)
+    total = ctypes.c_uint64(0)
+    st = L.kc_list(ctypes.byref(cd), k, _ptr(out), cap, ctypes.byref(total), _ptr(ws), ws.numel(), ctypes.byref(o),
+                   _stream_handle(stream))
+    t = int(total.value)
+    return st, t, out[:min(t, cap)]
+
+
+def list_cliques(d: Dag, k: int, cap: int | None = None, scheme: int = SCHEME_AUTO, ws: torch.Tensor | None = None,
+                 stream=None):
+    """(total, rows): the k-cliques of the DAG's graph (kc_list).  Without a cap
+    the output is sized by a count first, so every clique is listed."""
+    if cap is None:
+        cap = count(d, k, pivot=True, scheme=scheme) if k >= 3 else (d.n if k == 1 else d.m)
+    st, total, rows = list_cliques_status(d, k, cap, scheme, ws, stream)
+    if st != OK:
+        raise KcError(st, "kc_list")
+    return total, rows
 
 
 def count_noalloc_status(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, stream=None):

@@ -89,8 +89,10 @@ __global__ void __launch_bounds__(kBlock) k_classify(int nroots_total, int need,
                 int du = row_ptr[u + 1] - row_ptr[u] - 1;
                 int dv = row_ptr[v + 1] - row_ptr[v];
                 bound = du < dv ? du : dv;
+                if (du >= KC_MAX_DMAX) bound = -1;   // a wide root
             } else {
                 bound = row_ptr[r + 1] - row_ptr[r];
+                if (bound > KC_MAX_DMAX) bound = -1;                          // a wide root
             }
         }
         bool ok = r < nroots_total && bound >= need && bound >= 0;
@@ -119,11 +121,16 @@ __device__ __forceinline__ int width_list(int bound) {
 // |S| of root r: |N+(u)| for a vertex root; for the edge root (u, v) the size
 // of N+(u) ∩ N+(v), counted exactly (rows are ascending, and every common
 // vertex lies after v in the row of u).  Sizes below `need` are only bounded.
+// Wide roots (first vertex with more than KC_MAX_DMAX out-neighbours) give -1.
 template <bool EC>
 __device__ __forceinline__ int root_size(int r, int need, const int* __restrict__ row_ptr,
                                          const int* __restrict__ col, const int* __restrict__ src) {
-    if (!EC) return row_ptr[r + 1] - row_ptr[r];
+    if (!EC) {
+        const int s = row_ptr[r + 1] - row_ptr[r];
+        return s > KC_MAX_DMAX ? -1 : s;
+    }
     const int u = src[r], v = col[r];
+    if (row_ptr[u + 1] - row_ptr[u] > KC_MAX_DMAX) return -1;
     const int a0 = r + 1, na = row_ptr[u + 1] - a0;
     const int b0 = row_ptr[v], nb = row_ptr[v + 1] - b0;
     if (na < need || nb < need) return na < nb ? na : nb;
@@ -146,8 +153,9 @@ __device__ __forceinline__ int root_size(int r, int need, const int* __restrict_
 // Exact |S| of every edge root (u, v), one wavefront per source vertex u: the
 // row N+(u) is staged in LDS, then four 16-lane groups take the row's edges in
 // turn; a group reads N+(v) coalesced and binary-searches each entry in the tail
-// of N+(u) past v.  lst_of[r] gets the root's width list (-1 when |S| < need);
-// the list sizes go to ctl[CC_WN0 + j].  cap >= the longest DAG row.
+// of N+(u) past v.  lst_of[r] gets the root's width list (-1 when |S| < need,
+// and for the wide roots of rows longer than KC_MAX_DMAX); the list sizes go to
+// ctl[CC_WN0 + j].  cap >= the longest DAG row up to KC_MAX_DMAX.
 constexpr int kSizeWaves = 4;   // wavefronts per block
 __global__ void __launch_bounds__(64 * kSizeWaves) k_sizes_ec(int n, int need, const int* __restrict__ row_ptr,
                                                              const int* __restrict__ col,
@@ -165,6 +173,10 @@ __global__ void __launch_bounds__(64 * kSizeWaves) k_sizes_ec(int n, int need, c
     for (int u = blockIdx.x * kSizeWaves + static_cast<int>(threadIdx.x >> 6); u < n; u += nw) {
         const int b = row_ptr[u], du = row_ptr[u + 1] - b;
         if (du == 0) continue;
+        if (du > KC_MAX_DMAX) {
+            for (int i = lane; i < du; i += 64) lst_of[b + i] = -1;   // wide roots
+            continue;
+        }
         if (du > cap) {
             // a row longer than the stated d_max: per-edge search in global memory
             for (int i = lane; i < du; i += 64) {
@@ -537,13 +549,14 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         KC_CHECK(hipEventRecord(pe->ev[0], s));
     }
     const int nroots = ec ? d->m : d->n;
+    const int dm = bit_dmax(d->d_max);   // the on-chip kernels never see a wide root
     KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
     unsigned long long init[kAccWords] = {};
     init[0] = preload;
     for (int j = 0; j < kWidthLists; j++) init[6 + 4 * kWidthLists + 3 * j + 1] = ~0ull;   // min start of each list's timing
     KC_CHECK(hipMemcpyAsync(w.acc, init, sizeof(init), hipMemcpyHostToDevice, s));
     if (pivot_all >= 0) {
-        KC_CHECK(hipMemsetAsync(w.counts, 0, 2 * sizeof(unsigned long long) * (w.binom_n + 1), s));
+        KC_CHECK(hipMemsetAsync(w.counts, 0, 2 * sizeof(unsigned long long) * w.counts_len, s));
         // frame queues of the light and the heavy launch
         KC_CHECK(hipMemsetAsync(w.qctl, 0, sizeof(int) * kQueueCtlWords * 2, s));
         KC_CHECK(hipMemsetAsync(w.qready, 0, sizeof(int) * kQueueCap * 2, s));
@@ -561,7 +574,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
     if (lane_path) {
         // the widest list must fit one wavefront's LDS; otherwise use the group walk
         int top = 0;
-        while (top < kWidthLists - 1 && (32 << top) < d->d_max) top++;
+        while (top < kWidthLists - 1 && (32 << top) < dm) top++;
         const bool deep = k >= (ec ? 3 : 2) + 4;
         if (lane_lds_bytes(1 << top, k, ec, deep && top >= 1) > 160 * 1024) lane_path = false;
     }
@@ -574,7 +587,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             KC_CHECK(hipMemsetAsync(w.qready, 0, sizeof(int) * kQueueCap * kWidthLists, s));
         }
         if (ec) {
-            const int cap = d->d_max > 1 ? d->d_max : 1;
+            const int cap = dm > 1 ? dm : 1;
             int sblocks = div_up(d->n, kSizeWaves);
             if (sblocks > device_cus() * 8) sblocks = device_cus() * 8;
             if (sblocks < 1) sblocks = 1;
@@ -605,7 +618,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         const int p0 = ec ? 3 : 2;
         const bool deep = k >= p0 + 4;
         int top = 0;
-        while (top < kWidthLists - 1 && (32 << top) < d->d_max) top++;
+        while (top < kWidthLists - 1 && (32 << top) < dm) top++;
         // deep trees: the widest list runs on a side stream beside the others, so
         // that the tail of its few large roots overlaps their work
         SideGuard side;
@@ -699,19 +712,19 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         P.roots = w.light;
         P.nroots = w.ctl + CC_LIGHT_N;
         P.head = w.ctl + CC_LIGHT_HEAD;
-        int lw = pick_width(o, d->d_max, true);
+        int lw = pick_width(o, dm, true);
         if (lw > 8) lw = 8;
         st = ec ? launch_light<true>(P, lw, stats, s) : launch_light<false>(P, lw, stats, s);
         if (st != KC_OK) return st;
         if (prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
-        if (d->d_max > kLightCap) {
+        if (dm > kLightCap) {
             P.roots = w.heavy;
             P.nroots = w.ctl + CC_HEAVY_N;
             P.head = w.ctl + CC_HEAVY_HEAD;
             P.stats = w.acc + 4;
-            int wd = pick_width(o, d->d_max, false);
+            int wd = pick_width(o, dm, false);
             if (wd < 4) wd = 4;
-            st = ec ? launch_heavy<true>(P, wd, d->d_max, stats, s) : launch_heavy<false>(P, wd, d->d_max, stats, s);
+            st = ec ? launch_heavy<true>(P, wd, dm, stats, s) : launch_heavy<false>(P, wd, dm, stats, s);
             if (st != KC_OK) return st;
         }
     } else {
@@ -730,7 +743,7 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
             L.steal_after = o->handoff_after > 0 ? o->handoff_after : kPivStealAfter;
             L.cancel = const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel));
         }
-        L.d_max = d->d_max;
+        L.d_max = dm;
         L.row_ptr = d->row_ptr;
         L.col = d->col;
         L.src = d->src;
@@ -738,13 +751,19 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         st = pivot_launch(L, false, s);
         if (st != KC_OK) return st;
         if (prof) KC_CHECK(hipEventRecord(pe->ev[2], s));
-        if (d->d_max > kLightCap) {
+        if (dm > kLightCap) {
             st = pivot_launch(L, true, s);
             if (st != KC_OK) return st;
         }
     }
+    if (d->d_max > KC_MAX_DMAX && !lists && pivot_all != 2) {
+        // wide roots, after the others on the caller's stream
+        const int* cancel = o ? const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel)) : nullptr;
+        st = wide_launch(d, k, pivot_all < 0 ? 0 : pivot_all == 0 ? 1 : 2, w, cancel, s);
+        if (st != KC_OK) return st;
+    }
     if (prof) {
-        if (!lane_path && d->d_max <= kLightCap) KC_CHECK(hipEventRecord(pe->ev[2], s));
+        if (!lane_path && dm <= kLightCap) KC_CHECK(hipEventRecord(pe->ev[2], s));
         KC_CHECK(hipEventRecord(pe->ev[3], s));
     }
     KC_CHECK(hipMemcpyAsync(res, w.acc, kAccWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -842,7 +861,7 @@ int count_with_ws(const kc_dag* d, int32_t k, int32_t pivot, kc_u128* count, voi
         if (!pivot && count->hi) { count->hi = 0; return KC_EOVERFLOW; }
         return KC_OK;
     }
-    if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    if (d->d_max > KC_MAX_DMAX_WIDE) return KC_EUNSUPPORTED;
     size_t need = 0;
     CountWs w = carve_count(ws, d, pivot != 0, &need);
     if (!ws || ws_bytes < need) return KC_ENOMEM;
@@ -997,11 +1016,47 @@ extern "C" KC_API int32_t kc_count_local(const kc_dag* d, int32_t k, int32_t piv
     return KC_OK;
 }
 
+extern "C" KC_API int32_t kc_list(const kc_dag* d, int32_t k, int32_t* cliques, int64_t cap, uint64_t* total,
+                                  void* ws, size_t ws_bytes, const kc_opts* o, void* stream) {
+    if (!valid_dag(d) || !total || k < 1 || cap < 0 || (cap > 0 && !cliques) || (d->n > 0 && !d->perm))
+        return KC_EINVAL;
+    if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    *total = 0;
+    size_t need = 0;
+    CountWs w = carve_count(ws, d, false, &need);
+    if (!ws || ws_bytes < need) return KC_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (k == 1 || k == 2) {
+        const int st = list_orient_launch(d, k, false, cliques, cap, nullptr, nullptr, nullptr, s);
+        if (st != KC_OK) return st;
+        KC_CHECK(hipStreamSynchronize(s));
+        *total = k == 1 ? static_cast<uint64_t>(d->n) : static_cast<uint64_t>(d->m);
+        return KC_OK;
+    }
+    const int scheme = pick_scheme(o, k);
+    if (scheme != KC_SCHEME_VC && scheme != KC_SCHEME_EC) return KC_EINVAL;
+    const int* cancel = o ? const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel)) : nullptr;
+    KC_CHECK(hipMemsetAsync(w.ctl, 0, CC_WORDS * sizeof(int), s));
+    KC_CHECK(hipMemsetAsync(w.acc, 0, sizeof(unsigned long long), s));
+    const int st = list_orient_launch(d, k, scheme == KC_SCHEME_EC, cliques, cap, w.acc, w.ctl, cancel, s);
+    if (st != KC_OK) return st;
+    int hctl[CC_WORDS];
+    unsigned long long listed = 0;
+    KC_CHECK(hipMemcpyAsync(hctl, w.ctl, sizeof(hctl), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipMemcpyAsync(&listed, w.acc, sizeof(listed), hipMemcpyDeviceToHost, s));
+    KC_CHECK(hipStreamSynchronize(s));
+    if (hctl[CC_FLAGS] & kFlagCanceled) return KC_ECANCELED;
+    if (hctl[CC_FLAGS] & kFlagStalled) return KC_EDEVICE;
+    if (hctl[CC_FLAGS] & kFlagLocalOverflow) return KC_EOVERFLOW;
+    *total = listed;
+    return KC_OK;
+}
+
 extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* counts, int32_t cap,
                                        int32_t* omega, void* ws, size_t ws_bytes, const kc_opts* o,
                                        void* stream) {
     if (!valid_dag(d) || !counts || !omega || cap < 2) return KC_EINVAL;
-    if (d->d_max > KC_MAX_DMAX) return KC_EUNSUPPORTED;
+    if (d->d_max > KC_MAX_DMAX_WIDE) return KC_EUNSUPPORTED;
     if (!pivot) return count_all_orient(d, counts, cap, omega, ws, ws_bytes, o, static_cast<hipStream_t>(stream));
     size_t need = 0;
     CountWs w = carve_count(ws, d, true, &need);
@@ -1012,7 +1067,7 @@ extern "C" KC_API int32_t kc_count_all(const kc_dag* d, int32_t pivot, kc_u128* 
     bool ovf = false;
     if (d->m > 0 && d->d_max >= 2) {
         const int scheme = o && o->scheme == KC_SCHEME_EC ? KC_SCHEME_EC : KC_SCHEME_VC;
-        const int len = w.binom_n + 1;
+        const int len = w.counts_len;
         unsigned long long* host = new (std::nothrow) unsigned long long[2 * static_cast<size_t>(len)];
         if (!host) return KC_ENOMEM;
         unsigned long long res[kAccWords];

@@ -40,6 +40,8 @@ enum CountCtl {
     CC_LIGHT_HEAD = 2,   // light queue head
     CC_HEAVY_HEAD = 3,   // heavy queue head
     CC_FLAGS = 4,        // kFlag* bits
+    CC_WIDE_N = 5,       // wide root count
+    CC_WIDE_HEAD = 6,    // wide queue head
     CC_WN0 = 8,          // width lists: root counts (8..13)
     CC_WC0 = 16,         // width lists: fill cursors (16..21)
     CC_WH0 = 24,         // width lists: queue heads (24..29)
@@ -71,6 +73,21 @@ inline int maxw_for(int d_max) {
     return 32;
 }
 
+// The on-chip kernels see at most KC_MAX_DMAX out-neighbours per root: longer
+// out-rows make their roots wide (kc_wide.hip) and the others skip them.
+inline int bit_dmax(int d_max) { return d_max < KC_MAX_DMAX ? d_max : KC_MAX_DMAX; }
+
+// Wide roots: candidate slots and row words (padded to 4) of one wavefront's slab,
+// and the slab's words: rows, then per stack level the candidate and branch sets,
+// then 4 words of level scalars.
+inline int wide_s_cap(int d_max) { return ((d_max + 31) / 32) * 32; }
+inline int wide_wcap(int d_max) { return ((wide_s_cap(d_max) / 32) + 3) & ~3; }
+inline size_t wide_slab_words(int d_max) {
+    const size_t s = static_cast<size_t>(wide_s_cap(d_max)), w = static_cast<size_t>(wide_wcap(d_max));
+    return s * w + (s + 2) * (2 * w + 4);
+}
+constexpr size_t kWideSlabBudget = static_cast<size_t>(2) << 30;   // bytes of wide slabs at most
+
 inline int s_cap_for(int d_max) { return ((d_max + 31) / 32) * 32 > kLightCap ? ((d_max + 31) / 32) * 32 : kLightCap; }
 
 // Words of one pivot stack level: I, P_orig, P_remaining (maxw each) + p, np, nh, pad.
@@ -91,8 +108,13 @@ struct CountWs {
     int* qctl;                    // lane walk, subtree queue: kQueueCtlWords per width list
     int* qready;                  // lane walk, subtree queue: slot sequence words, kQueueCap per width list
     unsigned int* qitems;         // lane walk, subtree queue: kItemWords per slot, main + side
+    int* wide;                    // wide roots (d_max > KC_MAX_DMAX only)
+    unsigned int* wslabs;         // wide roots: one slab per wavefront
+    size_t wslab_words;
+    int nwslabs;
     int nactive;
     int binom_n;
+    int counts_len;               // entries of counts (sizes 0 .. counts_len - 1)
     size_t slab_words;
     int slabs;
 };
@@ -112,23 +134,43 @@ inline CountWs carve_count(void* ws, const kc_dag* d, bool pivot, size_t* bytes)
     w.qctl = c.take<int>(kQueueCtlWords * kWidthLists);
     w.qready = c.take<int>(static_cast<size_t>(kQueueCap) * kWidthLists);
     w.qitems = c.take<unsigned int>(2 * static_cast<size_t>(kQueueCap) * kItemWords);   // main and side stream
+    const int dm = bit_dmax(d->d_max);
     if (pivot) {
-        const int s_cap = s_cap_for(d->d_max);
+        const int s_cap = s_cap_for(dm);
         w.binom_n = s_cap + 2;
+        w.counts_len = w.binom_n + 1;
+        if (d->d_max > KC_MAX_DMAX && d->d_max + 3 > w.counts_len) w.counts_len = d->d_max + 3;
         const size_t cells = static_cast<size_t>(w.binom_n + 1) * (w.binom_n + 1);
-        w.counts = c.take<unsigned long long>(2 * static_cast<size_t>(w.binom_n + 1));
+        w.counts = c.take<unsigned long long>(2 * static_cast<size_t>(w.counts_len));
         w.binom = c.take<unsigned long long>(2 * cells);
         w.big = c.take<unsigned char>(cells);
-        if (d->d_max > kLightCap) {
-            const int maxw = maxw_for(d->d_max);
+        if (dm > kLightCap) {
+            const int maxw = maxw_for(dm);
             w.slab_words = static_cast<size_t>(s_cap + 2) * piv_level_words(maxw);
             w.slabs = device_cus() * kPivBlocksPerCU * 4;
             w.gstack = c.take<unsigned int>(w.slab_words * w.slabs);
         }
     }
+    if (d->d_max > KC_MAX_DMAX && d->d_max <= KC_MAX_DMAX_WIDE) {
+        w.wide = c.take<int>(static_cast<size_t>(d->n > 0 ? d->n : 1));
+        w.wslab_words = wide_slab_words(d->d_max);
+        size_t slabs = kWideSlabBudget / (4 * w.wslab_words);
+        const size_t most = static_cast<size_t>(device_cus()) * 2;
+        if (slabs > most) slabs = most;
+        if (slabs < 1) slabs = 1;
+        w.nwslabs = static_cast<int>(slabs);
+        w.wslabs = c.take<unsigned int>(w.wslab_words * slabs);
+    }
     *bytes = c.bytes();
     return w;
 }
+
+// Wide roots (kc_wide.hip): counts the cliques whose lowest vertex has more
+// than KC_MAX_DMAX out-neighbours, one vertex root per such vertex (the other
+// kernels skip these vertices' vertex and edge roots).  mode 0: graph
+// orientation with target k (adds to w.acc); 1: pivoting with target k (w.acc);
+// 2: pivoting, every size (w.counts).
+int wide_launch(const kc_dag* d, int k, int mode, const CountWs& w, const int* cancel, hipStream_t s);
 
 // Launch description for the pivot kernels (kc_pivot.hip).
 struct PivLaunch {
@@ -199,6 +241,12 @@ int lists_launch(const kc_dag* d, int k, bool ec, const CountWs& w, const int* c
 // count workspace's control block (zero at launch).
 int local_orient_launch(const kc_dag* d, int k, bool ec, unsigned long long* local, int* ctl, const int* cancel,
                         hipStream_t s);
+
+// k-clique listing by graph orientation (kc_local.hip): writes up to `cap` rows
+// of k input ids into `list` and counts every k-clique into *listed (device,
+// zero at launch); ctl is the count workspace's control block (zero at launch).
+int list_orient_launch(const kc_dag* d, int k, bool ec, int* list, long long cap, unsigned long long* listed,
+                       int* ctl, const int* cancel, hipStream_t s);
 
 // Capture-safe degree orientation (kc_orient.hip).
 size_t orient_async_workspace(int n, int nnz);

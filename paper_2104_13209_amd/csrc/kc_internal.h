@@ -113,6 +113,31 @@ __device__ __forceinline__ bool atomic_add_u128(unsigned long long* lo, unsigned
     return wrap;
 }
 
+// 128-bit value as four 32-bit limbs, little endian.
+struct U4 { unsigned int l[4]; };
+
+// x * m / d exactly, where d divides x * m; false when the result needs more
+// than 128 bits.  The product is formed in five limbs so that no intermediate
+// overflow is mistaken for an oversized result.
+__device__ inline bool muldiv(U4& x, unsigned int m, unsigned int d) {
+    unsigned int p[5];
+    unsigned long long carry = 0;
+    for (int i = 0; i < 4; i++) {
+        unsigned long long t = static_cast<unsigned long long>(x.l[i]) * m + carry;
+        p[i] = static_cast<unsigned int>(t);
+        carry = t >> 32;
+    }
+    p[4] = static_cast<unsigned int>(carry);
+    unsigned long long r = 0;
+    for (int i = 4; i >= 0; i--) {
+        unsigned long long cur = (r << 32) | p[i];
+        p[i] = static_cast<unsigned int>(cur / d);
+        r = cur % d;
+    }
+    for (int i = 0; i < 4; i++) x.l[i] = p[i];
+    return p[4] == 0;
+}
+
 // Wave-wide sum of a per-lane u64 into (lo, hi): exact, with carry detection.
 __device__ __forceinline__ void wave_sum_u128(unsigned long long v, unsigned long long& lo,
                                               unsigned long long& hi) {

@@ -38,7 +38,9 @@ enum Ctl {
     CTL_SIZE0 = 8,     // peel frontier sizes, ring of 3 (8, 9, 10)
     CTL_MIN = 11,      // peel level minimum
     CTL_HSIZE0 = 12,   // peel heavy-frontier sizes, ring of 3 (12, 13, 14)
-    CTL_WORDS = 16
+    CTL_AD_LIVE = 16,  // approximate degeneracy: vertices left
+    CTL_AD_SUM = 18,   // approximate degeneracy: their degree sum (u64 over words 18, 19)
+    CTL_WORDS = 20
 };
 
 // ------------------------------------------------------------ validation
@@ -305,6 +307,70 @@ __device__ int block_exclusive_scan(int x, int* total, int* sh /* >= kBlock/64 +
 // --------------------------------------------------------- exclusive scan
 
 // Pass 1: per-tile sums.  mode 0: sum of in[]; mode 1: count of radix zeros.
+// ------------------------------------------- approximate degeneracy order
+
+// A relaxation of k-core peeling (an orientation criterion named in Sec. 2;
+// the approximate peeling of ARB-COUNT with eps = 1/2): in rounds r = 0, 1, ...,
+// with L vertices left of total current degree D, every remaining vertex of
+// degree at most 1.5 D / L (2 deg L <= 3 D, exact in integers) leaves in round
+// r; afterwards its remaining neighbours lose one degree each.  The round is the
+// sort key, ties by id.  Rounds end when no vertex is left (each removes at
+// least one: the smallest degree is at most the average).
+
+__global__ void __launch_bounds__(kBlock) k_ad_init(int n, const int* __restrict__ row_ptr, int* deg, int* rnd,
+                                                   int* val) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        deg[v] = row_ptr[v + 1] - row_ptr[v];
+        rnd[v] = -1;
+        val[v] = v;
+    }
+}
+
+// L and D of the vertices still present.
+__global__ void __launch_bounds__(kBlock) k_ad_sum(int n, const int* __restrict__ deg, const int* __restrict__ rnd,
+                                                  int* ctl) {
+    const int lane = threadIdx.x & 63;
+    int live = 0;
+    unsigned long long dsum = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        if (rnd[v] < 0) {
+            live++;
+            dsum += static_cast<unsigned long long>(deg[v]);
+        }
+    }
+    live = wave_sum(live);
+    dsum = wave_sum(dsum);
+    if (lane == 0 && live) {
+        atomicAdd(&ctl[CTL_AD_LIVE], live);
+        atomicAdd(reinterpret_cast<unsigned long long*>(ctl + CTL_AD_SUM), dsum);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ad_mark(int n, int r, const int* __restrict__ deg, int* rnd,
+                                                   const int* __restrict__ ctl) {
+    const long long L = ctl[CTL_AD_LIVE];
+    const long long D = static_cast<long long>(*reinterpret_cast<const unsigned long long*>(ctl + CTL_AD_SUM));
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (rnd[v] < 0 && 2 * static_cast<long long>(deg[v]) * L <= 3 * D) rnd[v] = r;
+}
+
+// One wavefront per vertex that left in round r: its remaining neighbours lose
+// one degree each.
+__global__ void __launch_bounds__(kBlock) k_ad_dec(int n, int r, const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ col, int* deg,
+                                                  const int* __restrict__ rnd) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int v = wave; v < n; v += nwaves) {
+        if (rnd[v] != r) continue;
+        for (int j = row_ptr[v] + lane; j < row_ptr[v + 1]; j += 64) {
+            const int w = col[j];
+            if (rnd[w] < 0) atomicSub(&deg[w], 1);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_tile_sum(int count, const int* __restrict__ in, int bit,
                                                     int mode, int* tile_sum) {
     __shared__ int sh[kBlock / 64 + 1];
@@ -609,7 +675,8 @@ extern "C" KC_API size_t kc_orient_workspace(int32_t n, int32_t nnz, int32_t ord
 extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out, void* ws,
                                     size_t ws_bytes, int32_t validate, void* stream) {
     if (!g || !out) return KC_EINVAL;
-    if (order != KC_ORDER_DEGREE && order != KC_ORDER_DEGENERACY) return KC_EINVAL;
+    if (order != KC_ORDER_DEGREE && order != KC_ORDER_DEGENERACY && order != KC_ORDER_APPROX_DEGENERACY)
+        return KC_EINVAL;
     const int n = g->n, nnz = g->nnz;
     if (n < 0 || nnz < 0 || (nnz & 1)) return KC_EINVAL;
     if (!g->row_ptr || !out->row_ptr || (n > 0 && !out->perm)) return KC_EINVAL;
@@ -646,6 +713,28 @@ extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out,
     if (order == KC_ORDER_DEGREE) {
         k_degree_key<<<grid_for_threads(n), kBlock, 0, s>>>(n, g->row_ptr, w.key_a, w.val_a, w.ctl);
         KC_CHECK(hipGetLastError());
+    } else if (order == KC_ORDER_APPROX_DEGENERACY) {
+        // host-driven rounds: the live count decides when to stop
+        int* deg = w.key_b;   // scratch until the sort
+        k_ad_init<<<grid_for_threads(n), kBlock, 0, s>>>(n, g->row_ptr, deg, w.rnd, w.val_a);
+        KC_CHECK(hipGetLastError());
+        int r = 0;
+        for (;; r++) {
+            KC_CHECK(hipMemsetAsync(w.ctl + CTL_AD_LIVE, 0, 4 * sizeof(int), s));
+            k_ad_sum<<<grid_for_threads(n), kBlock, 0, s>>>(n, deg, w.rnd, w.ctl);
+            KC_CHECK(hipGetLastError());
+            int live = 0;
+            KC_CHECK(hipMemcpyAsync(&live, w.ctl + CTL_AD_LIVE, sizeof(int), hipMemcpyDeviceToHost, s));
+            KC_CHECK(hipStreamSynchronize(s));
+            if (live == 0) break;
+            k_ad_mark<<<grid_for_threads(n), kBlock, 0, s>>>(n, r, deg, w.rnd, w.ctl);
+            k_ad_dec<<<grid_for_waves(n), kBlock, 0, s>>>(n, r, g->row_ptr, g->col, deg, w.rnd);
+            KC_CHECK(hipGetLastError());
+        }
+        const int maxkey = r > 0 ? r - 1 : 0;
+        KC_CHECK(hipMemcpyAsync(w.ctl + CTL_MAXKEY, &maxkey, sizeof(int), hipMemcpyHostToDevice, s));
+        KC_CHECK(hipMemcpyAsync(w.ctl + CTL_ROUNDS, &r, sizeof(int), hipMemcpyHostToDevice, s));
+        KC_CHECK(hipMemcpyAsync(w.key_a, w.rnd, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
     } else {
         int occ = 0;
         KC_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel, kBlock, 0));

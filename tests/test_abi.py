@@ -64,6 +64,21 @@ def test_host_side_argument_checks(lib):
     assert L.kc_count_noalloc(ctypes.byref(big), 4, 0, ctypes.byref(res), None, None) == kc.ENOMEM
     assert L.kc_count_noalloc(ctypes.byref(big), 1, 0, ctypes.byref(res), None, None) == kc.OK
     assert (res.lo, res.hi) == (5_000_000, 0)
+    # out-degrees past the wide-root limit are refused before any device call;
+    # per-vertex counts stay within the on-chip limit
+    p1 = ctypes.c_void_p(1)
+    over = kc._Dag(20_000, 40_000, kc.MAX_DMAX_WIDE + 1, -1, 0, p1, p1, p1, p1)
+    wide = kc._Dag(20_000, 40_000, 2 * kc.MAX_DMAX, -1, 0, p1, p1, p1, p1)
+    chip = kc._Dag(20_000, 40_000, kc.MAX_DMAX, -1, 0, p1, p1, p1, p1)
+    for pivot in (0, 1):
+        assert L.kc_count(ctypes.byref(over), 4, pivot, ctypes.byref(res), p1, 1 << 40, None, None) == kc.EUNSUPPORTED
+    counts = (kc._U128 * 8)()
+    om = ctypes.c_int32(0)
+    assert L.kc_count_all(ctypes.byref(over), 1, counts, 7, ctypes.byref(om), p1, 1 << 40, None, None) == \
+        kc.EUNSUPPORTED
+    assert L.kc_count_local(ctypes.byref(wide), 4, 0, p1, p1, 1 << 40, None, None) == kc.EUNSUPPORTED
+    # wide roots add their global-memory slabs to the workspace
+    assert L.kc_count_workspace(ctypes.byref(wide), 4, 0, None) > L.kc_count_workspace(ctypes.byref(chip), 4, 0, None)
 
 
 def test_product_path_does_not_use_the_oracle():

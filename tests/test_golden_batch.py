@@ -1,7 +1,8 @@
 """The batched workload's count fixture (tests/golden/batch_counts_k5.txt)
 against what fixes it apart from the run that wrote it: the generator
-reproduces the batch's sizes; graphs of at most 64 vertices match the
-brute-force enumerator; a sample of the others matches the oracle's pivoting
+reproduces the batch's sizes; graphs of at most 64 vertices and edge density
+at most 1/2 match the brute-force enumerator (denser ones hold too many cliques
+to enumerate one by one); a sample of the others matches the oracle's pivoting
 recursion (Fig. 3) under degeneracy order, where the fixture used the plain
 recursion under degree order."""
 import os
@@ -31,8 +32,12 @@ def test_batch_fixture():
     assert len(c) == head["ngraphs"] == 10000 and head["k"] == 5
     b = synth.batch(head["ngraphs"], seed=4)
     assert (b.n, b.nnz) == (head["n"], head["nnz"])
-    small = [g for g in range(b.ngraphs) if b.graph(g).n <= 64]
-    assert small
+    small = []
+    for g in range(b.ngraphs):
+        n, m = b.graph(g).n, b.graph(g).nnz // 2
+        if n <= 64 and 4 * m <= n * (n - 1):
+            small.append(g)
+    assert len(small) >= 40
     for g in small[:40]:
         assert oracle.brute_counts(b.graph(g))[5] == c[g], g
     for g in range(0, b.ngraphs, 397):

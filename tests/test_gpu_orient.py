@@ -61,13 +61,32 @@ def test_degeneracy_order(kc, gi):
     assert d.d_max <= d.degeneracy
 
 
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_approx_degeneracy_order_matches_oracle(kc, gi):
+    # rounds of vertices at most 1.5 times the average degree: an integer rule,
+    # so the GPU relabelling equals the oracle's (round, id) order bit for bit
+    g = GRAPHS[gi]()
+    d = gpu_dag(kc, g, kc.ORDER_APPROX_DEGENERACY)
+    check_dag(kc, g, d)
+    od = oracle.orient(g, oracle.APPROX_DEGENERACY)
+    _, _, _, perm = kc.dag_to_host(d)
+    assert np.array_equal(perm, np.argsort(od.rank, kind="stable"))
+    assert d.d_max == od.d_max and d.degeneracy == -1
+    for k in (3, 4, 5):
+        want = oracle.count(od, k, False, oracle.VC)
+        assert kc.count(d, k, pivot=False) == want, k
+        assert kc.count(d, k, pivot=True) == want, k
+
+
 def test_config_powerlaw_orientation(kc):
     g = synth.config_powerlaw(wmax=5657.0)
-    for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY):
+    for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY):
         d = gpu_dag(kc, g, order)
         check_dag(kc, g, d)
         od = oracle.orient(g, order)
-        if order == kc.ORDER_DEGREE:
+        if order != kc.ORDER_DEGENERACY:
+            _, _, _, perm = kc.dag_to_host(d)
+            assert np.array_equal(perm, np.argsort(od.rank, kind="stable"))
             assert d.d_max == od.d_max
         else:
             assert d.degeneracy == od.degeneracy and d.d_max <= d.degeneracy
@@ -75,7 +94,7 @@ def test_config_powerlaw_orientation(kc):
 
 def test_empty_and_tiny(kc):
     for g in (synth.empty(1), synth.empty(7), synth.complete(2)):
-        for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY):
+        for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY):
             check_dag(kc, g, gpu_dag(kc, g, order))
 
 
