@@ -646,6 +646,48 @@ def main():
                             "bitset_speedup": round(pl.ms_total / pb.ms_total, 2), "same_count": cb == cl}
     log("ablation: %s" % ablation)
 
+    # orientation criteria (Sec. 3.1, Table 2's trade-off): orientation time, the
+    # DAG's out-degree bound and the count at k = 4 and 7 under each order
+    orders = {}
+    for name, oc in (("degree", kc.ORDER_DEGREE), ("degeneracy", kc.ORDER_DEGENERACY),
+                     ("approx_degeneracy", kc.ORDER_APPROX_DEGENERACY)):
+        ows_or = torch.empty(kc.orient_workspace_bytes(g.n, g.nnz, oc), dtype=torch.uint8, device=dev)
+        od = kc.orient(csr, oc, validate=False, ws=ows_or)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            kc.orient(csr, oc, validate=False, ws=ows_or, out=od)
+        e1.record()
+        e1.synchronize()
+        ent = {"orient_ms_no_validation": round(e0.elapsed_time(e1) / args.steps, 3), "d_max": od.d_max}
+        del ows_or
+        ows_o = torch.empty(kc.count_workspace_bytes(od, 7, False, kc.SCHEME_EC), dtype=torch.uint8, device=dev)
+        for k in (4, 7):
+            p = kc.Profile()
+            c = kc.count(od, k, scheme=kc.SCHEME_EC, ws=ows_o, profile=p)
+            ent[str(k)] = {"count_ms": round(p.ms_total, 3), "matches_oracle": (c == fix[k]) if k in fix else None}
+        orders[name] = ent
+        del ows_o
+        log("order %s: %s" % (name, ent))
+
+    # listing (kc_list): every triangle of the timed graph, 3 input ids per row
+    listing = None
+    if 3 in fix or args.n == 1_000_000:
+        c3 = kc.count(dag, 3, scheme=kc.SCHEME_EC, ws=cws)
+        rows_ws = torch.empty(kc.count_workspace_bytes(dag, 3, False, kc.SCHEME_EC), dtype=torch.uint8, device=dev)
+        kc.list_cliques(dag, 3, cap=c3, scheme=kc.SCHEME_EC, ws=rows_ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        total, rows = kc.list_cliques(dag, 3, cap=c3, scheme=kc.SCHEME_EC, ws=rows_ws)
+        e1.record()
+        e1.synchronize()
+        ms_l = e0.elapsed_time(e1)
+        listing = {"k": 3, "rows": int(total), "list_ms": round(ms_l, 3), "rows_per_s": total / (ms_l / 1e3),
+                   "output_GB_per_s": round(12.0 * total / (ms_l / 1e3) / 1e9, 2),
+                   "matches_oracle": (total == fix[3]) if 3 in fix else None}
+        del rows, rows_ws
+        log("listing: %s" % listing)
+
     literal = None
     if not args.no_literal and args.n == 1_000_000:
         log("literal w_max = 20000 leg ...")
@@ -697,6 +739,8 @@ def main():
         "cpu_baseline": cpu,
         "literal_wmax20000": literal,
         "ablation_no_bitsets": ablation,
+        "orientation_criteria": orders,
+        "listing": listing,
         "small": small,
         "batched": batched,
         "dense_core": dense,

@@ -180,10 +180,10 @@ KC_API size_t kc_orient_workspace(int32_t n, int32_t nnz, int32_t order);
  * (deg v, v)), KC_ORDER_DEGENERACY (k-core removal order from GPU peeling in
  * level-synchronous rounds; ties inside a round by id) or
  * KC_ORDER_APPROX_DEGENERACY (a relaxation of k-core, among the criteria of
- * Sec. 2: in rounds, every remaining vertex whose current degree is at most 1.5
- * times the remaining graph's average degree, i.e. 2 deg L <= 3 D for L
- * vertices of degree sum D, leaves at once; order by (round, id); fewer rounds
- * than exact peeling, out-degrees at most 3 times the degeneracy;
+ * Sec. 2: in rounds, every remaining vertex whose current degree is at most 1.1
+ * times the remaining graph's average degree, i.e. 10 deg L <= 11 D for L
+ * vertices of degree sum D, leaves at once; order by (round, id); far fewer
+ * rounds than exact peeling, out-degrees at most 2.2 times the degeneracy;
  * dag->degeneracy is -1 as for degree order).  Fills *out (device
  * arrays must hold n+1, m, m and n int32 with m = nnz/2) and its host fields;
  * synchronises `stream`.  validate != 0 first checks that g is a sorted simple

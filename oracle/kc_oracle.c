@@ -31,9 +31,9 @@
  *       smallest id first on ties (Matula-Beck); edge u->v iff u is removed first.
  *   R8  Approximate degeneracy order (a relaxation of k-core, one of the
  *       orientation criteria of Sec. 2; the rule of ARB-COUNT's approximate
- *       peeling with eps = 1/2): in rounds r = 0, 1, ..., with L vertices left
+ *       peeling with eps = 1/10): in rounds r = 0, 1, ..., with L vertices left
  *       of total current degree D, every remaining vertex whose degree is at
- *       most 1.5 D / L (2 deg L <= 3 D, exact in integers) leaves in round r;
+ *       most 1.1 D / L (10 deg L <= 11 D, exact in integers) leaves in round r;
  *       then the remaining neighbours of the leavers lose one degree each.  The
  *       order is by (round, id).
  *   R6  k = 1 gives n, k = 2 gives m (outside the pseudocode); counts[0] = 1 is
@@ -150,7 +150,7 @@ int kco_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int order,
                 if (round[v] < 0) { L++; D += deg[v]; }
             int32_t first = removed;
             for (int32_t v = 0; v < n; v++)
-                if (round[v] < 0 && 2 * (int64_t)deg[v] * L <= 3 * D) { round[v] = r; ids[removed++] = v; }
+                if (round[v] < 0 && 10 * (int64_t)deg[v] * L <= 11 * D) { round[v] = r; ids[removed++] = v; }
             for (int32_t i = first; i < removed; i++) {
                 int32_t v = ids[i];
                 for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)

@@ -310,12 +310,12 @@ __device__ int block_exclusive_scan(int x, int* total, int* sh /* >= kBlock/64 +
 // ------------------------------------------- approximate degeneracy order
 
 // A relaxation of k-core peeling (an orientation criterion named in Sec. 2;
-// the approximate peeling of ARB-COUNT with eps = 1/2): in rounds r = 0, 1, ...,
-// with L vertices left of total current degree D, every remaining vertex of
-// degree at most 1.5 D / L (2 deg L <= 3 D, exact in integers) leaves in round
-// r; afterwards its remaining neighbours lose one degree each.  The round is the
-// sort key, ties by id.  Rounds end when no vertex is left (each removes at
-// least one: the smallest degree is at most the average).
+// the approximate peeling of ARB-COUNT with eps = 1/10): in rounds r = 0, 1,
+// ..., with L vertices left of total current degree D, every remaining vertex
+// of degree at most 1.1 D / L (10 deg L <= 11 D, exact in integers) leaves in
+// round r; afterwards its remaining neighbours lose one degree each.  The round
+// is the sort key, ties by id.  Rounds end when no vertex is left (each removes
+// at least one: the smallest degree is at most the average).
 
 __global__ void __launch_bounds__(kBlock) k_ad_init(int n, const int* __restrict__ row_ptr, int* deg, int* rnd,
                                                    int* val) {
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kBlock) k_ad_mark(int n, int r, const int* __r
     const long long L = ctl[CTL_AD_LIVE];
     const long long D = static_cast<long long>(*reinterpret_cast<const unsigned long long*>(ctl + CTL_AD_SUM));
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        if (rnd[v] < 0 && 2 * static_cast<long long>(deg[v]) * L <= 3 * D) rnd[v] = r;
+        if (rnd[v] < 0 && 10 * static_cast<long long>(deg[v]) * L <= 11 * D) rnd[v] = r;
 }
 
 // One wavefront per vertex that left in round r: its remaining neighbours lose

@@ -63,7 +63,7 @@ def test_degeneracy_order(kc, gi):
 
 @pytest.mark.parametrize("gi", range(len(GRAPHS)))
 def test_approx_degeneracy_order_matches_oracle(kc, gi):
-    # rounds of vertices at most 1.5 times the average degree: an integer rule,
+    # rounds of vertices at most 1.1 times the average degree: an integer rule,
     # so the GPU relabelling equals the oracle's (round, id) order bit for bit
     g = GRAPHS[gi]()
     d = gpu_dag(kc, g, kc.ORDER_APPROX_DEGENERACY)
