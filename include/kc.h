@@ -305,12 +305,17 @@ typedef struct kc_batch {
 
 /* Execution plan by graph size: graphs with voff[g+1] - voff[g] <= n_hi[b] (the
  * first such bucket b, n_hi ascending) are counted with root scheme scheme[b]
- * (KC_SCHEME_VC / KC_SCHEME_EC); graphs above the last bound use the last
- * bucket.  Written by the autotuner; NULL = vertex roots for every graph. */
+ * (KC_SCHEME_VC / KC_SCHEME_EC) and traversal width[b]: 0 (or 1) = the lane walk
+ * (one lane per subtree), 2, 4, 8, 16 or 32 = sub-wavefront groups of that many
+ * lanes sharing each subtree (Sec. 3.5; lists of at most 64 candidates use
+ * groups of at most 8 lanes, wider lists of at least 4).  Graphs above the last
+ * bound use the last bucket.  Written by the autotuner; NULL = vertex roots and
+ * the lane walk for every graph. */
 typedef struct kc_batch_plan {
     int32_t nbuckets;
     int32_t n_hi[KC_BATCH_MAX_BUCKETS];
     int32_t scheme[KC_BATCH_MAX_BUCKETS];
+    int32_t width[KC_BATCH_MAX_BUCKETS];
 } kc_batch_plan;
 
 /* Bytes of device workspace kc_batch_count needs. */
@@ -322,7 +327,7 @@ KC_API size_t kc_batch_workspace(const kc_batch* b, int32_t k);
  * allocation and no memset, so the call can be captured in a HIP graph and
  * replayed.  A per-graph overflow past 2^64 leaves a non-zero hi word (the
  * caller's 64-bit check).  Returns KC_EINVAL for k < 1, bad sizes or a plan
- * with an unknown scheme, KC_ENOMEM for a short workspace, KC_EUNSUPPORTED if
+ * with an unknown scheme or width, KC_ENOMEM for a short workspace, KC_EUNSUPPORTED if
  * the out-degree bound min(max_degree, sqrt(2 max_graph_edges)) exceeds
  * KC_MAX_DMAX (rows could not be bitset-encoded). */
 KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t* counts, void* ws, size_t ws_bytes,

@@ -380,22 +380,24 @@ class _Batch(ctypes.Structure):
 
 
 class BatchPlan(ctypes.Structure):
-    """kc_batch_plan: root scheme per graph-size bucket (n <= n_hi[b])."""
+    """kc_batch_plan: root scheme and traversal width per graph-size bucket
+    (n <= n_hi[b]); width 0 = lane walk, 2..32 = sub-wavefront groups."""
     _fields_ = [("nbuckets", ctypes.c_int32), ("n_hi", ctypes.c_int32 * MAX_BUCKETS),
-                ("scheme", ctypes.c_int32 * MAX_BUCKETS)]
+                ("scheme", ctypes.c_int32 * MAX_BUCKETS), ("width", ctypes.c_int32 * MAX_BUCKETS)]
 
     @classmethod
     def make(cls, buckets):
-        """buckets: list of (n_hi, scheme) in ascending n_hi."""
+        """buckets: list of (n_hi, scheme) or (n_hi, scheme, width) in ascending n_hi."""
         p = cls()
         p.nbuckets = len(buckets)
-        for i, (hi, sc) in enumerate(buckets):
-            p.n_hi[i] = int(hi)
-            p.scheme[i] = int(sc)
+        for i, b in enumerate(buckets):
+            p.n_hi[i] = int(b[0])
+            p.scheme[i] = int(b[1])
+            p.width[i] = int(b[2]) if len(b) > 2 else 0
         return p
 
     def as_list(self):
-        return [(int(self.n_hi[i]), int(self.scheme[i])) for i in range(self.nbuckets)]
+        return [(int(self.n_hi[i]), int(self.scheme[i]), int(self.width[i])) for i in range(self.nbuckets)]
 
 
 @dataclass

@@ -1,10 +1,14 @@
-"""Autotuner for batched counting: root scheme per graph-size bucket.
+"""Autotuner for batched counting: root scheme and traversal width per
+graph-size bucket.
 
 Graphs of a batch are grouped into size buckets (by vertex count).  For each
-bucket, a sample of its graphs is packed into a sub-batch and timed with vertex
-roots and with edge roots (kc_batch_count, HIP-event timing after a warm-up
-call); the faster scheme wins.  The resulting plan can be saved as JSON and
-loaded later, keyed by the bucket bounds.
+bucket, a sample of its graphs is packed into a sub-batch and timed with every
+candidate (root scheme, traversal) pair: vertex or edge roots (Sec. 3.2), and
+the lane walk or sub-wavefront groups of 4 or 16 lanes (Sec. 3.5)
+(kc_batch_count, HIP-event timing after a warm-up call); the fastest pair wins.
+Sec. 4.5's guidelines (vertex roots and small groups for small graphs and small
+k) are the default order of the candidates, which decides ties.  The resulting
+plan can be saved as JSON and loaded later, keyed by the bucket bounds.
 """
 from __future__ import annotations
 
@@ -16,6 +20,7 @@ import torch
 from . import SCHEME_EC, SCHEME_VC, BatchPlan, batch_count_async, batch_to_device, batch_workspace_bytes
 
 DEFAULT_BOUNDS = (200, 1000, 1 << 30)
+WIDTHS = (0, 4, 16)   # lane walk, groups of 4 and 16 lanes
 
 
 def _sub_batch(b, graphs):
@@ -55,7 +60,7 @@ def _time_plan(bd, k, plan, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(b, k, bounds=DEFAULT_BOUNDS, sample=400, seed=0):
+def tune(b, k, bounds=DEFAULT_BOUNDS, sample=400, seed=0, widths=WIDTHS):
     """Plan for host batch b at clique size k; returns (BatchPlan, report dict)."""
     sizes = np.diff(b.voff.astype(np.int64))
     rng = np.random.default_rng(seed)
@@ -64,19 +69,22 @@ def tune(b, k, bounds=DEFAULT_BOUNDS, sample=400, seed=0):
     for hi in bounds:
         members = np.nonzero((sizes > lo) & (sizes <= hi))[0]
         if members.size == 0:
-            buckets.append((hi, SCHEME_VC))
+            buckets.append((hi, SCHEME_VC, 0))
             lo = hi
             continue
         pick = np.sort(rng.choice(members, size=min(sample, members.size), replace=False))
         bd = batch_to_device(_sub_batch(b, pick))
         t = {}
         for sc in (SCHEME_VC, SCHEME_EC):
-            t[sc] = _time_plan(bd, k, BatchPlan.make([(1 << 30, sc)]))
+            for wd in widths:
+                t[(sc, wd)] = _time_plan(bd, k, BatchPlan.make([(1 << 30, sc, wd)]))
         best = min(t, key=t.get)
-        buckets.append((hi, best))
+        buckets.append((hi, best[0], best[1]))
         report.append({"n_hi": int(hi), "graphs": int(members.size), "sampled": int(pick.size),
-                       "vc_ms": round(t[SCHEME_VC], 3), "ec_ms": round(t[SCHEME_EC], 3),
-                       "scheme": "VC" if best == SCHEME_VC else "EC"})
+                       "ms": {("VC" if sc == SCHEME_VC else "EC") + ("_lane" if wd == 0 else "_g%d" % wd):
+                              round(v, 3) for (sc, wd), v in t.items()},
+                       "scheme": "VC" if best[0] == SCHEME_VC else "EC",
+                       "width": int(best[1])})
         lo = hi
     return BatchPlan.make(buckets), report
 

@@ -4,11 +4,12 @@
 // The packed graphs form one disjoint union.  Orientation by degree order is
 // done once for the union (each graph's order is the restriction of the union's,
 // so every graph gets a valid orientation of its own).  Roots of every graph go
-// through one classification into width lists (vertex roots or edge roots per
-// the plan's choice for the graph's size bucket), and the persistent lane-walk
-// kernels pull them from device queues; each wavefront adds the partial counts of
-// a finished root to that root's graph counter.  No host synchronisation, no
-// memset and no device allocation happen inside the call.
+// through a classification into width lists, one pass per (root scheme,
+// traversal) pair that the plan assigns to some size bucket: vertex or edge
+// roots, and the lane walk or sub-wavefront groups of 2 to 32 lanes (Sec. 3.5).
+// The persistent kernels pull roots from device queues and add the partial
+// counts of a finished root to that root's graph counter.  No host
+// synchronisation, no memset and no device allocation happen inside the call.
 #include <cmath>
 
 #include "kc_count_impl.h"
@@ -45,14 +46,14 @@ __global__ void __launch_bounds__(kBlock) k_gid(int n, const int* __restrict__ p
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_graph_scheme(int ngraphs, const int* __restrict__ voff, kc_batch_plan plan,
-                                                        unsigned char* scheme) {
+__global__ void __launch_bounds__(kBlock) k_graph_bucket(int ngraphs, const int* __restrict__ voff, kc_batch_plan plan,
+                                                        unsigned char* bucket) {
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngraphs; g += gridDim.x * blockDim.x) {
         const int n = voff[g + 1] - voff[g];
         int b = plan.nbuckets - 1;
         for (int j = plan.nbuckets - 1; j >= 0; j--)
             if (n <= plan.n_hi[j]) b = j;
-        scheme[g] = static_cast<unsigned char>(plan.scheme[b]);
+        bucket[g] = static_cast<unsigned char>(b);
     }
 }
 
@@ -71,14 +72,15 @@ __device__ __forceinline__ int width_list_b(int bound) {
     return bound <= 32 ? 0 : bound <= 64 ? 1 : bound <= 128 ? 2 : bound <= 256 ? 3 : bound <= 512 ? 4 : 5;
 }
 
-// Width-list classification of the roots of graphs whose plan scheme matches:
-// pass 1 counts, pass 2 appends (as in the single-graph path).
+// Width-list classification of the roots of graphs whose size bucket is in
+// `buckets` (a bit mask): pass 1 counts, pass 2 appends (as in the single-graph
+// path).
 template <bool EC, bool FILL>
 __global__ void __launch_bounds__(kBlock) k_classify_batch(int nroots_total, int need, const int* __restrict__ row_ptr,
                                                           const int* __restrict__ col, const int* __restrict__ src,
                                                           const int* __restrict__ gid,
-                                                          const unsigned char* __restrict__ scheme, int* lists,
-                                                          int* ctl) {
+                                                          const unsigned char* __restrict__ bucket, unsigned buckets,
+                                                          int* lists, int* ctl) {
     const int lane = threadIdx.x & 63;
     int off[kWidthLists];
     if (FILL) {
@@ -88,13 +90,12 @@ __global__ void __launch_bounds__(kBlock) k_classify_batch(int nroots_total, int
             run += ctl[CC_WN0 + j];
         }
     }
-    const unsigned char want = EC ? KC_SCHEME_EC : KC_SCHEME_VC;
     for (int base = blockIdx.x * blockDim.x; base < nroots_total; base += gridDim.x * blockDim.x) {
         const int r = base + threadIdx.x;
         int lst = -1;
         if (r < nroots_total) {
             const int u = EC ? src[r] : r;
-            if (scheme[gid[u]] == want) {
+            if ((buckets >> bucket[gid[u]]) & 1u) {
                 int bound;
                 if (EC) {
                     const int v = col[r];
@@ -121,8 +122,8 @@ __global__ void __launch_bounds__(kBlock) k_classify_batch(int nroots_total, int
 struct BatchWs {
     void* orient_ws;
     int *dag_row_ptr, *dag_col, *dag_src, *perm, *gid;
-    unsigned char* scheme;
-    int* ctl[2];               // vertex-root and edge-root control words
+    unsigned char* bucket;     // size bucket of every graph
+    int* ctl[2];               // control words of alternate passes
     int* lists[2];
     int *task_ctr, *task_tot, *active;
     unsigned long long* acc;
@@ -141,11 +142,10 @@ BatchWs carve_batch(void* ws, const kc_batch* b, size_t* bytes) {
     w.dag_src = c.take<int>(static_cast<size_t>(m));
     w.perm = c.take<int>(static_cast<size_t>(n));
     w.gid = c.take<int>(static_cast<size_t>(n));
-    w.scheme = c.take<unsigned char>(static_cast<size_t>(b->ngraphs > 0 ? b->ngraphs : 1));
-    for (int i = 0; i < 2; i++) w.ctl[i] = c.take<int>(CC_WORDS);
-    w.lists[0] = c.take<int>(static_cast<size_t>(n));
-    w.lists[1] = c.take<int>(static_cast<size_t>(m));
+    w.bucket = c.take<unsigned char>(static_cast<size_t>(b->ngraphs > 0 ? b->ngraphs : 1));
     const int nr = n > m ? n : m;
+    for (int i = 0; i < 2; i++) w.ctl[i] = c.take<int>(CC_WORDS);
+    for (int i = 0; i < 2; i++) w.lists[i] = c.take<int>(static_cast<size_t>(nr));
     w.task_ctr = c.take<int>(static_cast<size_t>(nr));
     w.task_tot = c.take<int>(static_cast<size_t>(nr));
     w.nactive = device_cus() * kLaneWavesPerCU;
@@ -194,12 +194,16 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
     if (plan) {
         pl = *plan;
         if (pl.nbuckets < 1 || pl.nbuckets > KC_BATCH_MAX_BUCKETS) return KC_EINVAL;
-        for (int j = 0; j < pl.nbuckets; j++)
+        for (int j = 0; j < pl.nbuckets; j++) {
             if (pl.scheme[j] != KC_SCHEME_VC && pl.scheme[j] != KC_SCHEME_EC) return KC_EINVAL;
+            const int wd = pl.width[j];
+            if (wd < 0 || wd > 32 || (wd & (wd - 1)) != 0) return KC_EINVAL;
+        }
     } else {
         pl.nbuckets = 1;
         pl.n_hi[0] = 0x7fffffff;
         pl.scheme[0] = KC_SCHEME_VC;
+        pl.width[0] = 0;
     }
     size_t need = 0;
     BatchWs w = carve_batch(ws, b, &need);
@@ -219,7 +223,7 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
                                  w.orient_ws, s);
     if (st != KC_OK) return st;
     k_gid<<<grid_for(n), kBlock, 0, s>>>(n, w.perm, b->voff, G, w.gid);
-    k_graph_scheme<<<grid_for(G), kBlock, 0, s>>>(G, b->voff, pl, w.scheme);
+    k_graph_bucket<<<grid_for(G), kBlock, 0, s>>>(G, b->voff, pl, w.bucket);
     k_fill_i32<<<grid_for(w.nactive), kBlock, 0, s>>>(w.active, -1, w.nactive);
     k_fill_u64<<<1, kBlock, 0, s>>>(w.acc, 0ull, kAccWords);
     KC_CHECK(hipGetLastError());
@@ -227,11 +231,19 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
 
     int top = 0;
     while (top < kWidthLists - 1 && (32 << top) < out_bound) top++;
-    for (int pass = 0; pass < 2; pass++) {
-        const bool ec = pass == 1;
-        bool used = false;
-        for (int j = 0; j < pl.nbuckets; j++) used |= pl.scheme[j] == (ec ? KC_SCHEME_EC : KC_SCHEME_VC);
-        if (!used) continue;
+    // one pass per distinct (scheme, traversal) pair of the plan; passes run in
+    // stream order, so alternate passes may reuse the same lists
+    unsigned done_mask = 0;
+    int pass = -1;
+    for (int b0 = 0; b0 < pl.nbuckets; b0++) {
+        if ((done_mask >> b0) & 1u) continue;
+        const int width = pl.width[b0] <= 1 ? 0 : pl.width[b0];
+        unsigned buckets = 0;
+        for (int j = b0; j < pl.nbuckets; j++)
+            if (pl.scheme[j] == pl.scheme[b0] && (pl.width[j] <= 1 ? 0 : pl.width[j]) == width) buckets |= 1u << j;
+        done_mask |= buckets;
+        pass = (pass + 1) & 1;
+        const bool ec = pl.scheme[b0] == KC_SCHEME_EC;
         const int nroots = ec ? m : n;
         const int need_s = ec ? k - 2 : k - 1;
         const bool deep = k >= (ec ? 3 : 2) + 4;
@@ -243,16 +255,39 @@ extern "C" KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t*
         }
         if (ec) {
             k_classify_batch<true, false><<<grid_for(nroots), kBlock, 0, s>>>(
-                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.scheme, w.lists[pass], ctl);
+                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.bucket, buckets, w.lists[pass], ctl);
             k_classify_batch<true, true><<<grid_for(nroots), kBlock, 0, s>>>(
-                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.scheme, w.lists[pass], ctl);
+                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.bucket, buckets, w.lists[pass], ctl);
         } else {
             k_classify_batch<false, false><<<grid_for(nroots), kBlock, 0, s>>>(
-                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.scheme, w.lists[pass], ctl);
+                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.bucket, buckets, w.lists[pass], ctl);
             k_classify_batch<false, true><<<grid_for(nroots), kBlock, 0, s>>>(
-                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.scheme, w.lists[pass], ctl);
+                nroots, need_s, w.dag_row_ptr, w.dag_col, w.dag_src, w.gid, w.bucket, buckets, w.lists[pass], ctl);
         }
         KC_CHECK(hipGetLastError());
+        if (width >= 2) {
+            // sub-wavefront groups (Sec. 3.5), widest list first
+            for (int lst = top; lst >= 0; lst--) {
+                GoBatchLaunch B;
+                B.k = k;
+                B.ec = ec;
+                B.list = lst;
+                B.group = width;
+                B.row_ptr = w.dag_row_ptr;
+                B.col = w.dag_col;
+                B.src = w.dag_src;
+                B.lists = w.lists[pass];
+                B.list_counts = ctl + CC_WN0;
+                B.head = ctl + CC_WH0 + lst;
+                B.acc = w.acc;
+                B.flags = ctl + CC_FLAGS;
+                B.gacc = reinterpret_cast<unsigned long long*>(counts);
+                B.gid = w.gid;
+                st = go_batch_launch(B, s);
+                if (st != KC_OK) return st;
+            }
+            continue;
+        }
         for (int lst = top; lst >= 0; lst--) {
             LaneLaunch L;
             L.k = k;

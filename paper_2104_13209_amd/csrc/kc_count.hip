@@ -52,6 +52,10 @@ struct GoParams {
     int levels;                      // stack levels per group
     int* flags;                      // CC_FLAGS word (kFlagCanceled)
     const int* cancel;               // caller's cancel flag (null: none)
+    unsigned long long* gacc;        // batched: per-graph {lo, hi}; null otherwise
+    const int* gid;                  // batched: graph of each DAG vertex
+    const int* list_counts;          // batched: sizes of the width lists (roots = the lists back to back)
+    int list_index;                  // batched: the width list this launch walks
 };
 
 __device__ __forceinline__ int ffs64(unsigned long long x) { return __ffsll(static_cast<long long>(x)) - 1; }
@@ -300,7 +304,16 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
     const int stride = L.b_stride;
     const int k = P.k;
     const int p0 = EC ? 3 : 2;                          // path length of a task's root branch
-    const int nroots = *P.nroots;
+    const int* roots = P.roots;
+    int nroots = *P.nroots;
+    if (P.list_counts) {
+        // one width list of lists stored back to back: its offset is the sum of
+        // the sizes before it
+        int off = 0;
+        for (int j = 0; j < P.list_index; j++) off += P.list_counts[j];
+        roots += off;
+        nroots = P.list_counts[P.list_index];
+    }
 
     unsigned long long acc = 0;
     unsigned long long st_nodes = 0, st_words = 0;
@@ -318,7 +331,17 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
         team_sync<TW>();
         const int root = ctl[2];
         if (root >= nroots) break;
-        const int rid = P.roots[root];
+        const int rid = roots[root];
+        // batched: every lane adds this root's partial count to the root's graph
+        auto flush_graph = [&]() {
+            if (P.gacc) {
+                if (acc) {
+                    const int g = P.gid[EC ? P.src[rid] : rid];
+                    atomic_add_u128(P.gacc + 2 * g, P.gacc + 2 * g + 1, acc, 0ull);
+                }
+                acc = 0;
+            }
+        };
 
         // ---- candidate set S (sorted) and bitset rows B[i] (bit j <=> S[j] in N+(S[i]))
         extract_set<TW, EC>(rid, P.row_ptr, P.col, P.src, tl, S, &ctl[1]);
@@ -326,6 +349,7 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
         if (EC && k == 3) {
             // every vertex of S closes a triangle with the root edge
             if (tl == 0) acc += static_cast<unsigned long long>(s);
+            flush_graph();
             team_sync<TW>();
             continue;
         }
@@ -428,6 +452,7 @@ __global__ void __launch_bounds__(kBlock) k_go(GoParams P) {
                 }
             }
         }
+        flush_graph();
         team_sync<TW>();
     }
 
@@ -505,6 +530,43 @@ int launch_heavy(const GoParams& P, int width, int d_max, bool st, hipStream_t s
     if (d_max <= 512) return launch_heavy_w<EC, 16>(P, width, s_cap, st, s);
     return launch_heavy_w<EC, 32>(P, width, s_cap, st, s);
 }
+
+}  // namespace
+
+// Sub-wavefront group walk over one width list of a batched call (groups of
+// `group` lanes; lists 0 and 1 run a wavefront per root with at most 8 lanes
+// per group, wider lists a 4-wavefront team per root with at least 4).
+int go_batch_launch(const GoBatchLaunch& B, hipStream_t s) {
+    GoParams P;
+    P.n = 0;
+    P.m = 0;
+    P.k = B.k;
+    P.row_ptr = B.row_ptr;
+    P.col = B.col;
+    P.src = B.src;
+    P.roots = B.lists;
+    P.nroots = B.list_counts + B.list;
+    P.head = B.head;
+    P.acc = B.acc;
+    P.stats = B.acc + 2;
+    P.s_cap = 0;
+    P.levels = 0;
+    P.flags = B.flags;
+    P.cancel = nullptr;
+    P.gacc = B.gacc;
+    P.gid = B.gid;
+    P.list_counts = B.list_counts;
+    P.list_index = B.list;
+    if (B.list <= 1) {
+        const int g = B.group <= 2 ? 2 : B.group <= 4 ? 4 : 8;
+        return B.ec ? launch_light<true>(P, g, false, s) : launch_light<false>(P, g, false, s);
+    }
+    const int g = B.group <= 4 ? 4 : B.group <= 8 ? 8 : B.group <= 16 ? 16 : 32;
+    const int s_cap = 32 << B.list;
+    return B.ec ? launch_heavy<true>(P, g, s_cap, false, s) : launch_heavy<false>(P, g, s_cap, false, s);
+}
+
+namespace {
 
 bool valid_dag(const kc_dag* d) {
     if (!d || d->n < 0 || d->m < 0 || d->d_max < 0) return false;
@@ -712,6 +774,10 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         P.roots = w.light;
         P.nroots = w.ctl + CC_LIGHT_N;
         P.head = w.ctl + CC_LIGHT_HEAD;
+        P.gacc = nullptr;
+        P.gid = nullptr;
+        P.list_counts = nullptr;
+        P.list_index = 0;
         int lw = pick_width(o, dm, true);
         if (lw > 8) lw = 8;
         st = ec ? launch_light<true>(P, lw, stats, s) : launch_light<false>(P, lw, stats, s);

@@ -232,6 +232,27 @@ struct LaneLaunch {
 
 int lane_launch(const LaneLaunch& L, hipStream_t s);
 
+// Sub-wavefront group walk (k_go, Sec. 3.5) over one width list of a batched
+// call, adding each root's count to its graph's counter (kc_count.hip).
+struct GoBatchLaunch {
+    int k;
+    bool ec;
+    int list;                  // width list index (bitset words per row = 2^list)
+    int group;                 // lanes per group (2 .. 32)
+    const int* row_ptr;
+    const int* col;
+    const int* src;
+    const int* lists;          // all width lists back to back
+    const int* list_counts;    // ctl + CC_WN0
+    int* head;                 // ctl + CC_WH0 + list
+    unsigned long long* acc;   // scratch counters of the launch
+    int* flags;                // CC_FLAGS word
+    unsigned long long* gacc;  // per-graph {lo, hi}
+    const int* gid;            // graph of each DAG vertex
+};
+
+int go_batch_launch(const GoBatchLaunch& B, hipStream_t s);
+
 // Graph orientation over sorted candidate lists and binary-search
 // intersections instead of bitsets (kc_lists.hip; KC_OPT_NO_BITSETS).
 int lists_launch(const kc_dag* d, int k, bool ec, const CountWs& w, const int* cancel, hipStream_t s);

@@ -36,9 +36,23 @@ def test_batch_plans_agree(kc, small):
     bd = kc.batch_to_device(b)
     plans = [kc.BatchPlan.make([(1 << 30, kc.SCHEME_EC)]),
              kc.BatchPlan.make([(100, kc.SCHEME_VC), (250, kc.SCHEME_EC), (1 << 30, kc.SCHEME_VC)])]
+    # traversal widths: sub-wavefront groups of every size, alone and mixed with
+    # the lane walk across buckets and schemes
+    plans += [kc.BatchPlan.make([(1 << 30, sc, wd)]) for sc in (kc.SCHEME_VC, kc.SCHEME_EC)
+              for wd in (2, 4, 8, 16, 32)]
+    plans.append(kc.BatchPlan.make([(100, kc.SCHEME_VC, 0), (200, kc.SCHEME_EC, 4), (300, kc.SCHEME_VC, 16),
+                                    (1 << 30, kc.SCHEME_EC, 0)]))
     for plan in plans:
         for k in (3, 5, 7):
-            assert kc.batch_count(bd, k, plan) == [want[g][k] for g in range(b.ngraphs)]
+            assert kc.batch_count(bd, k, plan) == [want[g][k] for g in range(b.ngraphs)], (plan.as_list(), k)
+
+
+def test_batch_plan_rejects_bad_width(kc, small):
+    b, _ = small
+    bd = kc.batch_to_device(b)
+    for wd in (3, 64, -2):
+        with pytest.raises(kc.KcError):
+            kc.batch_count(bd, 4, kc.BatchPlan.make([(1 << 30, kc.SCHEME_VC, wd)]))
 
 
 def test_batch_dense_graphs(kc):
@@ -55,8 +69,9 @@ def test_batch_dense_graphs(kc):
     bd = kc.batch_to_device(b)
     for k in (4, 6, 7):
         want = [oracle.count(oracle.orient(g, oracle.DEGENERACY), k, True, oracle.VC) for g in graphs]
-        for plan in (None, kc.BatchPlan.make([(1 << 30, kc.SCHEME_EC)])):
-            assert kc.batch_count(bd, k, plan) == want, (k, plan)
+        for plan in (None, kc.BatchPlan.make([(1 << 30, kc.SCHEME_EC)]),
+                     kc.BatchPlan.make([(1 << 30, kc.SCHEME_VC, 8)]), kc.BatchPlan.make([(1 << 30, kc.SCHEME_EC, 32)])):
+            assert kc.batch_count(bd, k, plan) == want, (k, plan.as_list() if plan else None)
 
 
 def test_batch_graph_replay(kc, small):
@@ -97,7 +112,8 @@ def test_full_batch_matches_oracle_fixture(kc):
     assert (b.n, b.nnz) == (head["n"], head["nnz"])
     bd = kc.batch_to_device(b)
     assert bd.max_degree > kc.MAX_DMAX
-    for plan in (None, kc.BatchPlan.make([(200, kc.SCHEME_VC), (1000, kc.SCHEME_EC), (1 << 30, kc.SCHEME_VC)])):
+    for plan in (None, kc.BatchPlan.make([(200, kc.SCHEME_VC), (1000, kc.SCHEME_EC), (1 << 30, kc.SCHEME_VC)]),
+                 kc.BatchPlan.make([(200, kc.SCHEME_VC, 4), (1000, kc.SCHEME_VC, 0), (1 << 30, kc.SCHEME_EC, 16)])):
         got = kc.batch_count(bd, head["k"], plan)
         bad = [g for g in range(len(want)) if got[g] != want[g]]
-        assert not bad, (plan, bad[:10])
+        assert not bad, (plan.as_list() if plan else None, bad[:10])
