@@ -337,9 +337,12 @@ KC_API int32_t kc_batch_count(const kc_batch* b, int32_t k, uint64_t* counts, vo
 
 /* A query server over oriented graphs that stay resident on the device
  * (continuous batching).  Queries (graph, k, pivot) are admitted in arrival
- * order when one of `slots` workers is free and the query's workspace
- * (kc_count_workspace) fits in the server's device arena of `mem_budget` bytes;
- * admitted queries run concurrently, one HIP stream per worker, so work of
+ * order when one of `slots` workers is free, the query's workspace
+ * (kc_count_workspace) fits in the server's device arena of `mem_budget` bytes,
+ * and (unless no other query runs) the estimated LDS of the admitted queries
+ * stays within the device's LDS (per query: one wavefront's LDS for its widest
+ * root list or pivot kernel times the wavefronts it launches, at most one per
+ * root); admitted queries run concurrently, one HIP stream per worker, so work of
  * queries that arrive while others run overlaps on the device.  A query that
  * could never fit the arena completes at once with status KC_ENOMEM.
  * Ownership: the server allocates its arena and streams in kc_server_create and
@@ -357,6 +360,7 @@ typedef struct kc_query_result {
     double t_start;            /* admitted and started on a worker            */
     double t_done;             /* result on the host                          */
     uint64_t workspace;        /* bytes admitted against the arena            */
+    uint64_t lds;              /* estimated resident LDS bytes admitted       */
 } kc_query_result;
 
 KC_API int32_t kc_server_create(const kc_dag* dags, int32_t ndags, int32_t slots, uint64_t mem_budget,

@@ -510,7 +510,7 @@ class QueryResult(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("graph", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("pivot", ctypes.c_int32), ("status", ctypes.c_int32), ("count", _U128),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("workspace", ctypes.c_uint64)]
+                ("workspace", ctypes.c_uint64), ("lds", ctypes.c_uint64)]
 
     @property
     def value(self) -> int:

@@ -896,6 +896,40 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
 }
 
 }  // namespace
+
+size_t device_lds_bytes() {
+    int dev = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 160 * 1024;
+    return static_cast<size_t>(device_cus()) * static_cast<size_t>(per_cu);
+}
+
+size_t count_lds_demand(const kc_dag* d, int k, int pivot) {
+    if (!d || k < 3 || d->m <= 0 || k > d->d_max + 1) return 0;
+    const int dm = bit_dmax(d->d_max);
+    const bool ec = pick_scheme(nullptr, k) == KC_SCHEME_EC;
+    const long long roots = ec ? d->m : d->n;
+    size_t per_wave = 0;
+    long long waves = 0;
+    if (!pivot) {
+        int top = 0;
+        while (top < kWidthLists - 1 && (32 << top) < dm) top++;
+        const bool deep = k >= (ec ? 3 : 2) + 4;
+        per_wave = lane_lds_bytes(1 << top, k, ec, deep && top >= 1);
+        waves = static_cast<long long>(device_cus()) * kLaneWavesPerCU;
+    } else {
+        const int s_cap = s_cap_for(dm), maxw = maxw_for(dm);
+        per_wave = static_cast<size_t>(8 + s_cap + s_cap * b_stride_of(maxw)) * 4;
+        waves = static_cast<long long>(device_cus()) * kPivBlocksPerCU;
+    }
+    if (roots < waves) waves = roots;
+    const size_t total = per_wave * static_cast<size_t>(waves);
+    const size_t cap = device_lds_bytes();
+    return total < cap ? total : cap;
+}
+
 }  // namespace kc
 
 using namespace kc;

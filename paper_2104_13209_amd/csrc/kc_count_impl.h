@@ -232,6 +232,14 @@ struct LaneLaunch {
 
 int lane_launch(const LaneLaunch& L, hipStream_t s);
 
+// On-chip memory a kc_count call keeps resident while it runs (an estimate for
+// admission): the LDS bytes of one wavefront of its dominant traversal kernel
+// (the widest width list's lane walk, or the heavy pivot kernel) times the
+// wavefronts that kernel launches (at most one per root), capped at the device's
+// LDS (kc_count.hip).
+size_t count_lds_demand(const kc_dag* d, int k, int pivot);
+size_t device_lds_bytes();
+
 // Sub-wavefront group walk (k_go, Sec. 3.5) over one width list of a batched
 // call, adding each root's count to its graph's counter (kc_count.hip).
 struct GoBatchLaunch {

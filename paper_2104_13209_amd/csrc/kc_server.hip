@@ -2,12 +2,16 @@
 // graphs kept resident on the device.
 //
 // Queries are admitted in arrival order.  A query needs the workspace bytes
-// kc_count_workspace reports for its graph, k and mode; it is admitted when a
-// worker slot is free and a block of that size can be carved from the server's
-// device arena (first fit), so queries that arrive while others run start as
-// soon as slots and memory free up.  Every worker owns one HIP stream (default
-// priority); the kernels of concurrent queries overlap on the device.  A query
-// whose workspace exceeds the whole arena is refused (KC_ENOMEM) at once.
+// kc_count_workspace reports for its graph, k and mode, and an estimate of the
+// LDS its traversal keeps resident (one wavefront's rows and stacks times the
+// wavefronts it launches, at most one per root, capped at the device's LDS).  It
+// is admitted when a worker slot is free, a block of its workspace can be carved
+// from the server's device arena (first fit) and, unless nothing else runs, the
+// LDS of the admitted queries stays within the device's: many small queries run
+// side by side, a query that fills the device runs with few others.  Every
+// worker owns one HIP stream (default priority); the kernels of concurrent
+// queries overlap on the device.  A query whose workspace exceeds the whole
+// arena is refused (KC_ENOMEM) at once.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -17,7 +21,7 @@
 #include <thread>
 #include <vector>
 
-#include "kc_internal.h"
+#include "kc_count_impl.h"
 
 namespace kc {
 namespace {
@@ -31,6 +35,7 @@ struct Query {
     uint64_t ticket;
     int graph, k, pivot;
     size_t need;
+    size_t lds = 0;     // estimated resident LDS while running
     double t_submit, t_start = 0, t_done = 0;
     int status = KC_OK;
     kc_u128 count{0, 0};
@@ -87,6 +92,8 @@ struct kc_server {
     size_t arena_size = 0;
     kc::Arena* arena = nullptr;
     int slots = 1;
+    size_t lds_total = 0;                  // the device's LDS
+    size_t lds_used = 0;                   // estimated LDS of the admitted queries
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<kc::Query*> pending;        // not yet admitted, arrival order
@@ -103,8 +110,11 @@ struct kc_server {
     void admit_locked() {
         while (!pending.empty() && running + static_cast<int>(ready.size()) < slots) {
             kc::Query* q = pending.front();
+            const bool alone = running + static_cast<int>(ready.size()) == 0;
+            if (!alone && lds_used + q->lds > lds_total) break;   // wait for on-chip memory
             size_t off = 0;
             if (!arena->alloc(q->need, &off)) break;   // wait for memory (keep arrival order)
+            lds_used += q->lds;
             q->off = off;
             pending.pop_front();
             ready.push_back(q);
@@ -136,6 +146,7 @@ struct kc_server {
             {
                 std::lock_guard<std::mutex> lk(mu);
                 arena->release(q->off, q->need);
+                lds_used -= q->lds;
                 running--;
                 q->done = true;
                 admit_locked();
@@ -155,6 +166,7 @@ extern "C" KC_API int32_t kc_server_create(const kc_dag* dags, int32_t ndags, in
     sv->dags.assign(dags, dags + ndags);
     sv->slots = slots;
     sv->arena_size = mem_budget;
+    sv->lds_total = kc::device_lds_bytes();
     if (hipMalloc(reinterpret_cast<void**>(&sv->arena_mem), mem_budget) != hipSuccess) {
         delete sv;
         return KC_ENOMEM;
@@ -187,6 +199,7 @@ extern "C" KC_API int32_t kc_server_submit(kc_server* sv, int32_t graph, int32_t
     q->k = k;
     q->pivot = pivot ? 1 : 0;
     q->need = kc_count_workspace(&sv->dags[graph], k, q->pivot, nullptr);
+    q->lds = kc::count_lds_demand(&sv->dags[graph], k, q->pivot);
     q->t_submit = kc::now_s();
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) {
@@ -228,6 +241,7 @@ extern "C" KC_API int32_t kc_server_wait(kc_server* sv, uint64_t ticket, kc_quer
     res->t_start = q->t_start;
     res->t_done = q->t_done;
     res->workspace = q->need;
+    res->lds = q->lds;
     sv->all.erase(it);
     delete q;
     if (sv->stop && sv->waiters == 0) sv->cv_done.notify_all();   // kc_server_destroy may proceed

@@ -49,3 +49,26 @@ def test_memory_admission(kc, pool):
         # one at a time: no two runs overlap
         spans = sorted((r.t_start, r.t_done) for r in rs)
         assert all(spans[i][1] <= spans[i + 1][0] + 1e-3 for i in range(len(spans) - 1))
+
+
+def test_lds_admission(kc, pool):
+    import torch
+    graphs, dags = pool
+    # every query reports its estimated resident LDS.  A non-pivot count on a
+    # graph with 10,000 vertex roots and rows of 8 words (d_max 142) launches a
+    # full grid of lane-walk wavefronts of about 14 KB each: it claims more than
+    # half the device's LDS, so such queries run one at a time even with free
+    # slots and memory; a tiny graph's query claims a small fraction.
+    lds_dev = torch.cuda.get_device_properties(0).multi_processor_count * 160 * 1024
+    big = kc.orient(kc.to_device(synth.dense_core(10000, 8.0, 2.1, 2, 150, 180, 0.9, 7)), kc.ORDER_DEGENERACY)
+    assert 128 < big.d_max <= 256
+    tiny = kc.orient(kc.to_device(synth.erdos_renyi(40, 0.3, 1)), kc.ORDER_DEGREE)
+    want = kc.count(big, 5)
+    with kc.Server([big, tiny], slots=4, mem_budget=4 << 30) as sv:
+        rs = [sv.wait(t) for t in [sv.submit(0, 5) for _ in range(4)]]
+        small = sv.wait(sv.submit(1, 3))
+    assert all(r.status == kc.OK and r.value == want for r in rs)
+    assert all(2 * r.lds > lds_dev for r in rs)
+    assert small.status == kc.OK and 0 < small.lds < lds_dev // 100
+    spans = sorted((r.t_start, r.t_done) for r in rs)
+    assert all(spans[i][1] <= spans[i + 1][0] + 1e-3 for i in range(len(spans) - 1))
