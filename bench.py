@@ -135,6 +135,8 @@ def cpu_baseline(g, ks, frac, seed=0):
                              "est_count_s_one_core": round(dt_one * d.m / nsamp, 2)}
             total_all += dt_all * d.m / nsamp
             total_one += dt_one * d.m / nsamp
+        pool.close()
+        pool.join()   # the workers end before this process touches the GPU
     return {
         "value": g.m / total_all,
         "unit": "edges/s",
@@ -373,6 +375,8 @@ def served_pool(ngraphs, nmin, nmax, seed=5):
                 g = synth.chung_lu(n, 2.3, d, math.sqrt(d * n), gs)
         graphs.append(g)
         kinds.append(kind)
+        if (i + 1) % 25 == 0:
+            log("served pool: %d of %d graphs generated" % (i + 1, ngraphs))
     return graphs, kinds
 
 
@@ -399,7 +403,8 @@ def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, see
     # service rate of sequential launches, measured back to back on the warm-up queries
     with kc.Server(dags, slots=1, mem_budget=budget) as sv:
         t0 = time.perf_counter()
-        res = kc.replay_trace(sv, [(0.0, g, k, p) for g, k, p in qs[:nwarm]])
+        res = kc.replay_trace(sv, [(0.0, g, k, p) for g, k, p in qs[:nwarm]],
+                              progress=lambda c: log("served: %d warm-up results" % c))
         seq_rate = nwarm / (time.perf_counter() - t0)
     log("served: sequential service rate %.1f queries/s" % seq_rate)
     lam = util * seq_rate
@@ -413,9 +418,10 @@ def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, see
     for name, nslots in (("served", slots), ("sequential", 1), ("slots_2", 2), ("slots_4", 4)):
         if name.startswith("slots_") and nslots == slots:
             continue
+        log("served: %s pass (%d slots, about %.0f s of arrivals) ..." % (name, nslots, trace[-1][0]))
         with kc.Server(dags, slots=nslots, mem_budget=budget) as sv:
             t0 = time.perf_counter()
-            rs = kc.replay_trace(sv, trace)
+            rs = kc.replay_trace(sv, trace, progress=lambda c: log("served: %d results" % c))
             span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
         lat = [r.latency * 1e3 for r in rs]
         log("served: %s pass done (%.1f s)" % (name, span))
@@ -432,7 +438,8 @@ def bench_served(kc, ngraphs, nmin, nmax, nq, nwarm, slots, budget_gb, util, see
     # saturation: every query submitted at once (closed loop), throughput only
     for name, nslots in (("served_saturated", slots), ("sequential_saturated", 1)):
         with kc.Server(dags, slots=nslots, mem_budget=budget) as sv:
-            rs = kc.replay_trace(sv, [(0.0, g, k, p) for _, g, k, p in trace])
+            rs = kc.replay_trace(sv, [(0.0, g, k, p) for _, g, k, p in trace],
+                                 progress=lambda c: log("served: %d results" % c))
             span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
         log("served: %s pass done (%.1f s)" % (name, span))
         out[name] = {"queries_per_s": len(rs) / span}

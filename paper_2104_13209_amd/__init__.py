@@ -584,9 +584,10 @@ class Server:
             pass
 
 
-def replay_trace(server: Server, trace):
+def replay_trace(server: Server, trace, progress=None):
     """Submit (t_arrival_s, graph, k, pivot) queries at their arrival offsets from
-    now (open loop) and return the results in submission order."""
+    now (open loop) and return the results in submission order.  progress, if
+    given, is called with the number of results collected every 25 results."""
     import time
     t0 = time.perf_counter()
     tickets = []
@@ -597,4 +598,9 @@ def replay_trace(server: Server, trace):
                 break
             time.sleep(min(dt, 0.002) if dt > 0.0005 else 0)
         tickets.append(server.submit(g, k, piv))
-    return [server.wait(t) for t in tickets]
+    out = []
+    for t in tickets:
+        out.append(server.wait(t))
+        if progress is not None and len(out) % 25 == 0:
+            progress(len(out))
+    return out
