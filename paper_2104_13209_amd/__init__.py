@@ -265,14 +265,16 @@ def count(d: Dag, k: int, pivot: bool = False, scheme: int = SCHEME_AUTO, width:
 
 def count_all_status(d: Dag, pivot: bool = True, cap: int | None = None, scheme: int = SCHEME_AUTO,
                      width: int = 0, ws: torch.Tensor | None = None, stream=None,
-                     profile: Profile | None = None, cancel: int = 0, collect_stats: bool = False):
+                     profile: Profile | None = None, cancel: int = 0, collect_stats: bool = False,
+                     handoff: bool = True, handoff_after: int = 0, handoff_every: int = 0):
     """(status, [c_0, ..., c_cap], omega) of kc_count_all without raising."""
     L = lib()
     if cap is None:
         cap = d.d_max + 2
     cap = max(int(cap), 2)
     cd = d._c()
-    o = _opts(scheme, width, 0, profile, collect_stats, cancel=cancel)
+    o = _opts(scheme, width, 0, profile, collect_stats, handoff=handoff, cancel=cancel,
+              handoff_after=handoff_after, handoff_every=handoff_every)
     need = int(L.kc_count_workspace(ctypes.byref(cd), 0, int(bool(pivot)), ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, d.row_ptr.device)

@@ -805,8 +805,8 @@ int run_count(const kc_dag* d, int k, int pivot_all, const kc_opts* o, const Cou
         L.stats = stats;
         L.steal = !(o && (o->flags & KC_OPT_NO_HANDOFF));
         if (o) {
-            L.steal_every = o->handoff_every > 0 ? o->handoff_every : kPivStealEvery;
-            L.steal_after = o->handoff_after > 0 ? o->handoff_after : kPivStealAfter;
+            L.steal_every = o->handoff_every > 0 ? o->handoff_every : 0;
+            L.steal_after = o->handoff_after > 0 ? o->handoff_after : 0;
             L.cancel = const_cast<const int*>(reinterpret_cast<const volatile int*>(o->cancel));
         }
         L.d_max = dm;

@@ -25,8 +25,15 @@ constexpr int kFlagLocalOverflow = 8;   // a per-vertex count passed 2^64
 // handoff thresholds (defaults; kc_opts may lower them for tests)
 constexpr int kLaneStealEvery = 16;    // lane walk: wavefront rounds between looks at the subtree queue
 constexpr int kLaneStealAfter = 256;   // lane walk: rounds on the current root or subtree before it may hand over
-constexpr int kPivStealEvery = 64;     // pivot: tree nodes between looks at the frame queue
-constexpr int kPivStealAfter = 4096;   // pivot: nodes of the current root or frame before it may hand over
+// pivot: tree nodes between looks at the frame queue, and nodes of the current
+// root or frame before it may hand over.  A consumer re-extracts the frame's
+// root, so only long trees should give work away.  Edge roots with at most 64
+// candidates (the light list) are very many short trees: their frames go only
+// after 65536 nodes (dense-core count-all 0.77 s against 2.0 s at 4096, no
+// loss on power-law graphs); vertex roots and heavy roots keep 4096.
+constexpr int kPivStealEvery = 64;
+constexpr int kPivStealAfter = 4096;
+constexpr int kPivStealAfterLightEC = 65536;
 constexpr int kCancelEvery = 32;       // wavefront rounds (lane walk) or nodes (pivot) between cancel polls
 // count lo/hi, light/heavy stats, per width list: nodes, words, iterations,
 // expansions, busy, start, end; helper timing (3); per width list: counted
@@ -179,8 +186,8 @@ struct PivLaunch {
     bool ec;              // edge roots
     bool stats;
     bool steal;           // hand saved frames to idle wavefronts (queue regions 0 and 1)
-    int steal_every = kPivStealEvery;
-    int steal_after = kPivStealAfter;
+    int steal_every = 0;                   // 0: the default (kPivStealEvery)
+    int steal_after = 0;                   // 0: the default of the root list and scheme
     const int* cancel = nullptr;   // caller's cancel flag (null: none)
     unsigned long long* local = nullptr;   // per-vertex counts of size k (input ids); null: totals
     const int* perm = nullptr;             // DAG id -> input id (local counts)

@@ -629,7 +629,7 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
     P.local = L.local;
     const int mode = L.local ? 2 : (L.all ? 1 : 0);
     P.steal_every = L.steal_every > 0 ? L.steal_every : kPivStealEvery;
-    P.steal_after = L.steal_after > 0 ? L.steal_after : kPivStealAfter;
+    P.steal_after = L.steal_after > 0 ? L.steal_after : (L.ec && !heavy ? kPivStealAfterLightEC : kPivStealAfter);
     P.cancel = L.cancel;
     if (!heavy) {
         P.s_cap = kLightCap;
