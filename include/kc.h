@@ -7,8 +7,8 @@
  * whose vertices are pairwise adjacent.
  *
  * Pipeline behind this header:
- *   kc_orient   orient G into a DAG by degree, degeneracy or approximate
- *               degeneracy order (Sec. 3.1),
+ *   kc_orient   orient G into a DAG by degree, degeneracy, approximate
+ *               degeneracy or colouring order (Sec. 3.1),
  *               filter edges and rebuild the CSR by histogram + exclusive scan;
  *   kc_list     list the k-cliques themselves (the orientation traversal);
  *   kc_count    traverse one search tree per root vertex (vertex-centric) or root
@@ -53,7 +53,7 @@ typedef enum kc_status {
     KC_EUNSUPPORTED = -6   /* graph exceeds a documented limit of this build     */
 } kc_status;
 
-enum { KC_ORDER_DEGREE = 0, KC_ORDER_DEGENERACY = 1, KC_ORDER_APPROX_DEGENERACY = 2 };
+enum { KC_ORDER_DEGREE = 0, KC_ORDER_DEGENERACY = 1, KC_ORDER_APPROX_DEGENERACY = 2, KC_ORDER_COLOR = 3 };
 enum { KC_SCHEME_AUTO = 0, KC_SCHEME_VC = 1, KC_SCHEME_EC = 2 };
 
 /* Largest out-degree whose roots keep their bitset rows on chip (LDS,
@@ -184,7 +184,13 @@ KC_API size_t kc_orient_workspace(int32_t n, int32_t nnz, int32_t order);
  * times the remaining graph's average degree, i.e. 10 deg L <= 11 D for L
  * vertices of degree sum D, leaves at once; order by (round, id); far fewer
  * rounds than exact peeling, out-degrees at most 2.2 times the degeneracy;
- * dag->degeneracy is -1 as for degree order).  Fills *out (device
+ * dag->degeneracy is -1 as for degree order) or KC_ORDER_COLOR (graph
+ * colouring, also among the criteria of Sec. 2: the greedy first-fit colouring
+ * in decreasing order of the priority SplitMix64(v) (its output function applied
+ * to v + 0x9E3779B97F4A7C15; ties by the larger id), computed by Jones-Plassmann
+ * rounds; order by (colour, id), so every edge leaves its lower colour;
+ * degeneracy -1; out-degrees are not bounded by the degeneracy and can exceed
+ * KC_MAX_DMAX on skewed graphs).  Fills *out (device
  * arrays must hold n+1, m, m and n int32 with m = nnz/2) and its host fields;
  * synchronises `stream`.  validate != 0 first checks that g is a sorted simple
  * symmetric CSR and returns KC_EINVAL if not; with validate == 0 a malformed

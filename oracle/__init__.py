@@ -24,7 +24,7 @@ _SRCS = [os.path.join(_HERE, "kc_oracle.c"), os.path.join(_HERE, "kc_brute.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-DEGREE, DEGENERACY, APPROX_DEGENERACY = 0, 1, 2
+DEGREE, DEGENERACY, APPROX_DEGENERACY, COLOR = 0, 1, 2, 3
 VC, EC = 1, 2
 OK, EINVAL, ENOMEM, EOVERFLOW = 0, -1, -2, -3
 
@@ -63,8 +63,11 @@ def _load():
         lib.kco_count_local.argtypes = [i32, i32p, i32p, i32p, i32p, i32, i32, ctypes.c_int,
                                         ctypes.c_int, u64p]
         lib.kco_brute_counts.argtypes = [i32, i32p, i32p, i32, u64p]
+        lib.kco_colour.argtypes = [i32, i32p, i32p, i32p]
+        lib.kco_splitmix64.argtypes = [ctypes.c_uint64]
+        lib.kco_splitmix64.restype = ctypes.c_uint64
         for f in (lib.kco_validate, lib.kco_orient, lib.kco_count, lib.kco_count_all,
-                  lib.kco_count_local, lib.kco_brute_counts):
+                  lib.kco_count_local, lib.kco_brute_counts, lib.kco_colour):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -127,6 +130,23 @@ def orient(g, order: int = DEGREE) -> Dag:
     if st != OK:
         raise OracleError(st, "orient")
     return Dag(n, out_ptr, out_col[:m], rank[:n], dmax.value, degen.value, rp, cl)
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64's output for counter value x (the colouring priority)."""
+    return int(_load().kco_splitmix64(x & ((1 << 64) - 1)))
+
+
+def colour(g) -> np.ndarray:
+    """Greedy first-fit colouring in decreasing (priority, id) order."""
+    lib = _load()
+    rp, cl = _i32(g.row_ptr), _i32(g.col)
+    clp = cl if cl.size else np.zeros(1, dtype=np.int32)
+    out = np.zeros(max(g.n, 1), dtype=np.int32)
+    st = lib.kco_colour(g.n, _p(rp), _p(clp), _p(out))
+    if st != OK:
+        raise OracleError(st, "colour")
+    return out[:g.n]
 
 
 def _dag_args(d: Dag):

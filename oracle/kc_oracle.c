@@ -36,6 +36,13 @@
  *       most 1.1 D / L (10 deg L <= 11 D, exact in integers) leaves in round r;
  *       then the remaining neighbours of the leavers lose one degree each.  The
  *       order is by (round, id).
+ *   R9  Colouring order (graph colouring, one of the orientation criteria of
+ *       Sec. 2): vertices are coloured greedily, each with the smallest colour
+ *       absent from its already coloured neighbours, visiting them by decreasing
+ *       priority p(v) and then decreasing id, where p(v) is SplitMix64's output
+ *       for the counter value v (its mixing function applied to v plus the
+ *       golden-ratio increment 0x9E3779B97F4A7C15; Steele, Lea and Flood,
+ *       OOPSLA 2014).  The order is by (colour, id).
  *   R6  k = 1 gives n, k = 2 gives m (outside the pseudocode); counts[0] = 1 is
  *       the empty clique.
  *   R7  Counts are unsigned 128-bit; any carry out of bit 127 sets an overflow flag.
@@ -51,7 +58,7 @@
 typedef unsigned __int128 u128;
 
 enum { KCO_OK = 0, KCO_EINVAL = -1, KCO_ENOMEM = -2, KCO_EOVERFLOW = -3 };
-enum { KCO_DEGREE = 0, KCO_DEGENERACY = 1, KCO_APPROX_DEGENERACY = 2 };
+enum { KCO_DEGREE = 0, KCO_DEGENERACY = 1, KCO_APPROX_DEGENERACY = 2, KCO_COLOR = 3 };
 enum { KCO_VC = 1, KCO_EC = 2 };
 
 /* ------------------------------------------------------------------ input */
@@ -85,6 +92,47 @@ static int cmp_degree_id(const void* a, const void* b) {
     int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
     if (g_deg_for_sort[x] != g_deg_for_sort[y]) return g_deg_for_sort[x] < g_deg_for_sort[y] ? -1 : 1;
     return (x > y) - (x < y);
+}
+
+/* R9: SplitMix64 output for counter value x: the mixing function of the
+ * generator applied to x + 0x9E3779B97F4A7C15. */
+uint64_t kco_splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static const uint64_t* g_prio_for_sort;
+/* decreasing (priority, id) */
+static int cmp_priority_desc(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    uint64_t px = g_prio_for_sort[x], py = g_prio_for_sort[y];
+    if (px != py) return px > py ? -1 : 1;
+    return (x < y) - (x > y);
+}
+
+/* R9: greedy first-fit colouring in decreasing (priority, id) order; colour[v]
+ * receives v's colour (0-based). */
+int kco_colour(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* colour) {
+    int32_t* ids = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+    uint64_t* prio = (uint64_t*)malloc((size_t)(n ? n : 1) * sizeof(uint64_t));
+    char* taken = (char*)calloc((size_t)n + 1, 1);
+    if (!ids || !prio || !taken) { free(ids); free(prio); free(taken); return KCO_ENOMEM; }
+    for (int32_t v = 0; v < n; v++) { prio[v] = kco_splitmix64((uint64_t)v); ids[v] = v; colour[v] = -1; }
+    g_prio_for_sort = prio;
+    qsort(ids, (size_t)n, sizeof(int32_t), cmp_priority_desc);
+    for (int32_t i = 0; i < n; i++) {
+        int32_t v = ids[i], c = 0;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+            if (colour[col[e]] >= 0) taken[colour[col[e]]] = 1;
+        while (taken[c]) c++;
+        colour[v] = c;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+            if (colour[col[e]] >= 0) taken[colour[col[e]]] = 0;
+    }
+    free(ids); free(prio); free(taken);
+    return KCO_OK;
 }
 
 /* Binary min-heap of (key, id) with lazy deletion, for the degeneracy peel. */
@@ -127,7 +175,8 @@ static int64_t heap_pop(heap64* h) {
 int kco_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int order,
                int32_t* out_ptr, int32_t* out_col, int32_t* rank,
                int32_t* d_max, int32_t* degeneracy) {
-    if (n < 0 || (order != KCO_DEGREE && order != KCO_DEGENERACY && order != KCO_APPROX_DEGENERACY))
+    if (n < 0 || (order != KCO_DEGREE && order != KCO_DEGENERACY && order != KCO_APPROX_DEGENERACY &&
+                  order != KCO_COLOR))
         return KCO_EINVAL;
     int32_t* ids = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
     int32_t* deg = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
@@ -135,6 +184,12 @@ int kco_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int order,
     for (int32_t v = 0; v < n; v++) deg[v] = row_ptr[v + 1] - row_ptr[v];
     *degeneracy = -1;
     if (order == KCO_DEGREE) {
+        for (int32_t v = 0; v < n; v++) ids[v] = v;
+        g_deg_for_sort = deg;
+        qsort(ids, (size_t)n, sizeof(int32_t), cmp_degree_id);
+    } else if (order == KCO_COLOR) {
+        /* R9: sort by (colour, id); deg[] is reused to hold the colours */
+        if (kco_colour(n, row_ptr, col, deg) != KCO_OK) { free(ids); free(deg); return KCO_ENOMEM; }
         for (int32_t v = 0; v < n; v++) ids[v] = v;
         g_deg_for_sort = deg;
         qsort(ids, (size_t)n, sizeof(int32_t), cmp_degree_id);

@@ -23,7 +23,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libkc.so")
 
-ORDER_DEGREE, ORDER_DEGENERACY, ORDER_APPROX_DEGENERACY = 0, 1, 2
+ORDER_DEGREE, ORDER_DEGENERACY, ORDER_APPROX_DEGENERACY, ORDER_COLOR = 0, 1, 2, 3
 SCHEME_AUTO, SCHEME_VC, SCHEME_EC = 0, 1, 2
 OPT_NO_HANDOFF, OPT_SINGLE_STREAM, OPT_NO_BITSETS = 1, 2, 4
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ECANCELED, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6

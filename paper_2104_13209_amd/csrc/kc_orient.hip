@@ -38,6 +38,8 @@ enum Ctl {
     CTL_SIZE0 = 8,     // peel frontier sizes, ring of 3 (8, 9, 10)
     CTL_MIN = 11,      // peel level minimum
     CTL_HSIZE0 = 12,   // peel heavy-frontier sizes, ring of 3 (12, 13, 14)
+    CTL_CL_SIZE0 = 8,  // colouring: light frontier sizes, ring of 3 (8, 9, 10; not used with the peel)
+    CTL_CL_HSIZE0 = 12,// colouring: heavy frontier sizes, ring of 3 (12, 13, 14)
     CTL_AD_LIVE = 16,  // approximate degeneracy: vertices left
     CTL_AD_SUM = 18,   // approximate degeneracy: their degree sum (u64 over words 18, 19)
     CTL_WORDS = 20
@@ -371,6 +373,158 @@ __global__ void __launch_bounds__(kBlock) k_ad_dec(int n, int r, const int* __re
     }
 }
 
+// ---------------------------------------------------------- colouring order
+
+// Graph colouring as an orientation criterion (Sec. 2 names it): vertices get
+// the greedy first-fit colour in decreasing order of a pseudo-random priority
+// (SplitMix64's output for the vertex id; the output function is a bijection, so
+// priorities never tie), and the order is (colour, id); adjacent vertices differ
+// in colour, so every edge goes from its lower colour to its higher one.
+//
+// The sequential greedy colouring is reproduced in Jones-Plassmann rounds kept
+// as a countdown: hp[v] counts v's neighbours of higher priority that are not
+// coloured yet, a vertex is coloured in the round after its count reaches zero
+// (the first round for counts that start at zero), and then decrements its
+// lower-priority neighbours.  Each vertex's colour depends only on its
+// higher-priority neighbours, all coloured in earlier rounds, so the result is
+// the greedy one and the total work is O(m) over however many rounds (the
+// longest decreasing-priority path: 943 on the 1M-vertex power-law graph).
+
+__device__ __forceinline__ unsigned long long colour_priority(int v) {
+    unsigned long long z = static_cast<unsigned long long>(v) + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Frontiers are split by degree: a light vertex (degree <= kClHeavy) is coloured
+// by one wavefront, a heavy one by a whole block, because the rounds are serial
+// and almost every one of them holds a hub of thousands of neighbours.
+constexpr int kClHeavy = 512;
+
+struct ClFront {
+    int* light;        // this round's light vertices
+    int* heavy;        // and heavy ones
+    int* next_light;   // the next round's
+    int* next_heavy;
+};
+
+__device__ __forceinline__ void cl_append(int u, const int* row_ptr, const ClFront& f, int* ctl, int r) {
+    if (row_ptr[u + 1] - row_ptr[u] > kClHeavy)
+        f.next_heavy[atomicAdd(&ctl[CTL_CL_HSIZE0 + (r + 1) % 3], 1)] = u;
+    else
+        f.next_light[atomicAdd(&ctl[CTL_CL_SIZE0 + (r + 1) % 3], 1)] = u;
+}
+
+// One wavefront per vertex: hp[v] = higher-priority neighbours; the vertices
+// with none form round 0's frontier (sizes in ring slot 0).
+__global__ void __launch_bounds__(kBlock) k_cl_init(int n, const int* __restrict__ row_ptr,
+                                                   const int* __restrict__ col, int* hp, int* val, ClFront f,
+                                                   int* ctl) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int v = wave; v < n; v += nwaves) {
+        const unsigned long long pv = colour_priority(v);
+        int c = 0;
+        for (int j = row_ptr[v] + lane; j < row_ptr[v + 1]; j += 64)
+            c += colour_priority(col[j]) > pv;
+        c = wave_sum(c);
+        if (lane == 0) {
+            hp[v] = c;
+            val[v] = v;
+            if (c == 0) cl_append(v, row_ptr, f, ctl, -1);
+        }
+    }
+}
+
+// Colour v with the T threads of a wavefront (T = 64, sync = wave_sync_lds) or a
+// block (T = kBlock, sync = __syncthreads), t = the thread's index among them:
+// first fit over the colours of v's higher-priority neighbours in windows of
+// 1024 (an LDS bitmap; every wavefront reads the whole bitmap, so all of them
+// find the same colour), then count down the lower-priority neighbours.  The
+// neighbour loops keep four loads in flight per thread.
+template <int T, typename Sync>
+__device__ __forceinline__ int cl_colour_vertex(int v, int t, unsigned int* used, const int* __restrict__ row_ptr,
+                                                const int* __restrict__ col, int* hp, int* colour, const ClFront& f,
+                                                int* ctl, int r, Sync sync) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long pv = colour_priority(v);
+    const int b = row_ptr[v], e = row_ptr[v + 1];
+    int c = -1;
+    for (int base = 0; c < 0; base += 1024) {
+        if (t < 32) used[t] = 0u;
+        sync();
+        for (int j0 = b + t; j0 < e; j0 += U * T) {
+            int u[U];
+#pragma unroll
+            for (int q = 0; q < U; q++) u[q] = j0 + q * T < e ? col[j0 + q * T] : -1;
+            int cu[U];
+#pragma unroll
+            for (int q = 0; q < U; q++) cu[q] = u[q] >= 0 && colour_priority(u[q]) > pv ? colour[u[q]] - base : -1;
+#pragma unroll
+            for (int q = 0; q < U; q++)
+                if (cu[q] >= 0 && cu[q] < 1024) atomicOr(&used[cu[q] >> 5], 1u << (cu[q] & 31));
+        }
+        sync();
+        const unsigned int free_bits = lane < 32 ? ~used[lane] : 0u;
+        const unsigned long long m = __ballot(free_bits != 0u);
+        if (m) {
+            const int w = __ffsll(static_cast<long long>(m)) - 1;
+            const unsigned int fw =
+                static_cast<unsigned int>(__builtin_amdgcn_readlane(static_cast<int>(free_bits), w));
+            c = base + 32 * w + __ffs(static_cast<int>(fw)) - 1;
+        }
+        sync();
+    }
+    if (t == 0) colour[v] = c;
+    for (int j0 = b + t; j0 < e; j0 += U * T) {
+        int u[U];
+#pragma unroll
+        for (int q = 0; q < U; q++) u[q] = j0 + q * T < e ? col[j0 + q * T] : -1;
+        bool z[U];
+#pragma unroll
+        for (int q = 0; q < U; q++) z[q] = u[q] >= 0 && colour_priority(u[q]) < pv && atomicSub(&hp[u[q]], 1) == 1;
+#pragma unroll
+        for (int q = 0; q < U; q++)
+            if (z[q]) cl_append(u[q], row_ptr, f, ctl, r);
+    }
+    return c;
+}
+
+// Round r: colour this round's frontier and build the next one.  Sizes live in
+// rings of three slots (light: CTL_CL_SIZE0, heavy: CTL_CL_HSIZE0): this round
+// reads slot r % 3, appends to slot (r + 1) % 3 (cleared by round r - 1) and
+// clears slot (r + 2) % 3, which only the finished round r - 1 read.  A fixed
+// grid strides over the frontier (blocks over the heavy list, then wavefronts
+// over the light one), so the host launches rounds without reading sizes back.
+__global__ void __launch_bounds__(kBlock) k_cl_round(int r, ClFront f, const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col, int* hp, int* colour, int* ctl) {
+    __shared__ unsigned int used_all[kBlock / 64][32];
+    const int lane = threadIdx.x & 63;
+    const int count = ctl[CTL_CL_SIZE0 + r % 3];
+    const int hcount = ctl[CTL_CL_HSIZE0 + r % 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl[CTL_CL_SIZE0 + (r + 2) % 3] = ctl[CTL_CL_HSIZE0 + (r + 2) % 3] = 0;
+        if (count + hcount > 0) atomicMax(&ctl[CTL_ROUNDS], r + 1);
+    }
+    int mx = 0;
+    for (int h = blockIdx.x; h < hcount; h += gridDim.x) {
+        const int c = cl_colour_vertex<kBlock>(f.heavy[h], threadIdx.x, used_all[0], row_ptr, col, hp, colour, f,
+                                               ctl, r, [] { __syncthreads(); });
+        mx = c > mx ? c : mx;
+    }
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int i = wave; i < count; i += nwaves) {
+        const int c = cl_colour_vertex<64>(f.light[i], lane, used_all[threadIdx.x >> 6], row_ptr, col, hp, colour, f,
+                                           ctl, r, [] { wave_sync_lds(); });
+        mx = c > mx ? c : mx;
+    }
+    if (lane == 0 && mx > 0) atomicMax(&ctl[CTL_MAXKEY], mx);
+}
+
 __global__ void __launch_bounds__(kBlock) k_tile_sum(int count, const int* __restrict__ in, int bit,
                                                     int mode, int* tile_sum) {
     __shared__ int sh[kBlock / 64 + 1];
@@ -535,23 +689,53 @@ __global__ void __launch_bounds__(kBlock) k_fill(int n, const int* __restrict__ 
     }
 }
 
+// One block per row longer than kRowCap: rows up to kLongSortCap entries are
+// bitonic-sorted in LDS (entries are distinct new ids; the padding is INT_MAX);
+// longer ones place each entry at its rank, counted over the row in global memory.
+constexpr int kLongSortCap = 8192;
+
 __global__ void __launch_bounds__(kBlock) k_sort_long_rows(int n, const int* __restrict__ dag_ptr,
                                                           const int* __restrict__ tmp, int* dag_col,
                                                           int* dag_src) {
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (int i = wave; i < n; i += nwaves) {
+    __shared__ int buf[kLongSortCap];
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int base = dag_ptr[i];
         const int len = dag_ptr[i + 1] - base;
         if (len <= kRowCap) continue;
         const int* row = tmp + base;
-        for (int t = lane; t < len; t += 64) {
-            int x = row[t];
-            int below = 0;
-            for (int q = 0; q < len; q++) below += row[q] < x;
-            dag_col[base + below] = x;
-            dag_src[base + below] = i;
+        if (len <= kLongSortCap) {
+            int p = 1;
+            while (p < len) p <<= 1;
+            for (int t = threadIdx.x; t < p; t += kBlock) buf[t] = t < len ? row[t] : INT_MAX;
+            __syncthreads();
+            for (int k = 2; k <= p; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int t = threadIdx.x; t < p; t += kBlock) {
+                        const int o = t ^ j;
+                        if (o > t) {
+                            const int x = buf[t], y = buf[o];
+                            if ((x > y) == ((t & k) == 0)) {
+                                buf[t] = y;
+                                buf[o] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int t = threadIdx.x; t < len; t += kBlock) {
+                dag_col[base + t] = buf[t];
+                dag_src[base + t] = i;
+            }
+            __syncthreads();
+        } else {
+            for (int t = threadIdx.x; t < len; t += kBlock) {
+                const int x = row[t];
+                int below = 0;
+                for (int q = 0; q < len; q++) below += row[q] < x;
+                dag_col[base + below] = x;
+                dag_src[base + below] = i;
+            }
         }
     }
 }
@@ -654,7 +838,7 @@ int orient_degree_async(int n, int nnz, const int* row_ptr, const int* col, int 
     if (nnz > 0) {
         k_fill<<<grid_for_waves(n), kBlock, 0, s>>>(n, row_ptr, col, out_perm, w.rank, out_row_ptr, out_col,
                                                    out_src, w.tmp, w.ctl);
-        k_sort_long_rows<<<grid_for_waves(n), kBlock, 0, s>>>(n, out_row_ptr, w.tmp, out_col, out_src);
+        k_sort_long_rows<<<grid_for_threads(n), kBlock, 0, s>>>(n, out_row_ptr, w.tmp, out_col, out_src);
         KC_CHECK(hipGetLastError());
     }
     return KC_OK;
@@ -675,7 +859,8 @@ extern "C" KC_API size_t kc_orient_workspace(int32_t n, int32_t nnz, int32_t ord
 extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out, void* ws,
                                     size_t ws_bytes, int32_t validate, void* stream) {
     if (!g || !out) return KC_EINVAL;
-    if (order != KC_ORDER_DEGREE && order != KC_ORDER_DEGENERACY && order != KC_ORDER_APPROX_DEGENERACY)
+    if (order != KC_ORDER_DEGREE && order != KC_ORDER_DEGENERACY && order != KC_ORDER_APPROX_DEGENERACY &&
+        order != KC_ORDER_COLOR)
         return KC_EINVAL;
     const int n = g->n, nnz = g->nnz;
     if (n < 0 || nnz < 0 || (nnz & 1)) return KC_EINVAL;
@@ -713,6 +898,27 @@ extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out,
     if (order == KC_ORDER_DEGREE) {
         k_degree_key<<<grid_for_threads(n), kBlock, 0, s>>>(n, g->row_ptr, w.key_a, w.val_a, w.ctl);
         KC_CHECK(hipGetLastError());
+    } else if (order == KC_ORDER_COLOR) {
+        // the colours go straight into the sort keys; rounds are launched in
+        // batches of 4, 8, ... 64, and the host reads the frontier size after each
+        k_cl_init<<<grid_for_waves(n), kBlock, 0, s>>>(n, g->row_ptr, g->col, w.rnd, w.val_a,
+                                                       ClFront{nullptr, nullptr, w.fr0, w.hf0}, w.ctl);
+        KC_CHECK(hipGetLastError());
+        const int grid = device_cus() * 4;
+        int r = 0;
+        for (int batch = 4;; batch = batch < 64 ? 2 * batch : 64) {
+            for (int i = 0; i < batch; i++, r++) {
+                const ClFront f = (r & 1) ? ClFront{w.fr1, w.hf1, w.fr0, w.hf0} : ClFront{w.fr0, w.hf0, w.fr1, w.hf1};
+                k_cl_round<<<grid, kBlock, 0, s>>>(r, f, g->row_ptr, g->col, w.rnd, w.key_a, w.ctl);
+            }
+            KC_CHECK(hipGetLastError());
+            int left[2] = {0, 0};
+            KC_CHECK(hipMemcpyAsync(&left[0], w.ctl + CTL_CL_SIZE0 + r % 3, sizeof(int), hipMemcpyDeviceToHost, s));
+            KC_CHECK(hipMemcpyAsync(&left[1], w.ctl + CTL_CL_HSIZE0 + r % 3, sizeof(int), hipMemcpyDeviceToHost, s));
+            KC_CHECK(hipStreamSynchronize(s));
+            if (left[0] + left[1] == 0) break;
+            if (r > n) return KC_EDEVICE;   // cannot happen: every round colours at least one vertex
+        }
     } else if (order == KC_ORDER_APPROX_DEGENERACY) {
         // host-driven rounds: the live count decides when to stop
         int* deg = w.key_b;   // scratch until the sort
@@ -793,7 +999,7 @@ extern "C" KC_API int32_t kc_orient(const kc_csr* g, int32_t order, kc_dag* out,
     KC_CHECK(hipMemcpyAsync(&total, out->row_ptr + n, sizeof(int), hipMemcpyDeviceToHost, s));
     KC_CHECK(hipStreamSynchronize(s));
     if (hctl[CTL_LONG]) {
-        k_sort_long_rows<<<grid_for_waves(n), kBlock, 0, s>>>(n, out->row_ptr, w.tmp, out->col, out->src);
+        k_sort_long_rows<<<grid_for_threads(n), kBlock, 0, s>>>(n, out->row_ptr, w.tmp, out->col, out->src);
         KC_CHECK(hipGetLastError());
         KC_CHECK(hipStreamSynchronize(s));
     }

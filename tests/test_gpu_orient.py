@@ -78,9 +78,61 @@ def test_approx_degeneracy_order_matches_oracle(kc, gi):
         assert kc.count(d, k, pivot=True) == want, k
 
 
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_colour_order_matches_oracle(kc, gi):
+    # the greedy colouring by decreasing priority is unique (the priority is a
+    # bijection of the id), so the Jones-Plassmann rounds must reproduce the
+    # oracle's sequential colouring and its (colour, id) order bit for bit
+    g = GRAPHS[gi]()
+    d = gpu_dag(kc, g, kc.ORDER_COLOR)
+    check_dag(kc, g, d)
+    od = oracle.orient(g, oracle.COLOR)
+    _, _, _, perm = kc.dag_to_host(d)
+    assert np.array_equal(perm, np.argsort(od.rank, kind="stable"))
+    assert d.d_max == od.d_max and d.degeneracy == -1
+    for k in (3, 4, 5):
+        want = oracle.count(od, k, False, oracle.VC)
+        assert kc.count(d, k, pivot=False) == want, k
+        assert kc.count(d, k, pivot=True) == want, k
+
+
+def test_colour_order_complete_graph(kc):
+    # K_n takes n rounds (one vertex per round) and n colours; d_max = n - 1 is
+    # beyond the LDS limit, so the counts run through the wide roots
+    import math
+    n = 1500
+    g = synth.complete(n)
+    d = gpu_dag(kc, g, kc.ORDER_COLOR)
+    _, _, _, perm = kc.dag_to_host(d)
+    assert np.array_equal(perm, np.argsort(oracle.orient(g, oracle.COLOR).rank, kind="stable"))
+    assert d.d_max == n - 1
+    assert kc.count(d, 3, pivot=False) == math.comb(n, 3)
+    assert kc.count(d, 6, pivot=True) == math.comb(n, 6)
+
+
+def test_long_rows_sorted(kc):
+    # DAG rows beyond 1024 entries are sorted by a block per row: bitonic in LDS
+    # up to 8192 entries, rank placement beyond.  K_3000 in degree order has rows
+    # of every length up to 2999; a star whose centre has the highest colouring
+    # priority takes colour 0, so its row holds all 9000 leaves
+    g = synth.complete(3000)
+    d = gpu_dag(kc, g, kc.ORDER_DEGREE)
+    check_dag(kc, g, d)
+    assert d.d_max == 2999
+    leaves = 9000
+    centre = max(range(leaves + 1), key=lambda v: (oracle.splitmix64(v), v))
+    star = synth.from_pairs(leaves + 1, [(centre, v) for v in range(leaves + 1) if v != centre])
+    d = gpu_dag(kc, star, kc.ORDER_COLOR)
+    check_dag(kc, star, d)
+    assert d.d_max == leaves
+    _, _, _, perm = kc.dag_to_host(d)
+    assert perm[0] == centre
+    assert np.array_equal(perm, np.argsort(oracle.orient(star, oracle.COLOR).rank, kind="stable"))
+
+
 def test_config_powerlaw_orientation(kc):
     g = synth.config_powerlaw(wmax=5657.0)
-    for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY):
+    for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY, kc.ORDER_COLOR):
         d = gpu_dag(kc, g, order)
         check_dag(kc, g, d)
         od = oracle.orient(g, order)
@@ -94,7 +146,7 @@ def test_config_powerlaw_orientation(kc):
 
 def test_empty_and_tiny(kc):
     for g in (synth.empty(1), synth.empty(7), synth.complete(2)):
-        for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY):
+        for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY, kc.ORDER_COLOR):
             check_dag(kc, g, gpu_dag(kc, g, order))
 
 

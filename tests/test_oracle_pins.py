@@ -326,6 +326,89 @@ def test_approx_degeneracy_bound_and_counts():
                 assert oracle.count(da, k, False, oracle.VC) == oracle.count(dd, k, True, oracle.EC)
 
 
+# --------------------------------------------------------- colouring order
+
+def test_splitmix64_published_vectors():
+    # SplitMix64 seeded with 0 first returns 0xE220A8397B1DCDAF; seeded with
+    # 1234567 it returns the five values below (outputs of its published
+    # reference implementation).  The oracle's function is the output for the
+    # state before the increment, so the i-th output is f(seed + (i - 1) gamma).
+    gamma = 0x9E3779B97F4A7C15
+    assert oracle.splitmix64(0) == 0xE220A8397B1DCDAF
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    got = [oracle.splitmix64((1234567 + i * gamma) % 2 ** 64) for i in range(5)]
+    assert got == want
+
+
+def _priority_order(n):
+    return sorted(range(n), key=lambda v: (oracle.splitmix64(v), v), reverse=True)
+
+
+def test_colouring_closed_forms():
+    # K_n: every vertex sees all earlier ones, so its colour is its place in the
+    # decreasing-priority order, and the orientation follows that order
+    n = 40
+    c = oracle.colour(synth.complete(n))
+    order = _priority_order(n)
+    assert [int(c[v]) for v in order] == list(range(n))
+    d = oracle.orient(synth.complete(n), oracle.COLOR)
+    assert [int(d.rank[v]) for v in order] == list(range(n))
+    # complete multipartite: greedy gives every part one colour (vertices of a
+    # part have equal neighbourhoods), so exactly as many colours as parts, and
+    # parts are coloured in the order their first vertex appears
+    parts = (3, 1, 4, 1, 5, 9, 2, 6)
+    g = synth.complete_multipartite(parts)
+    c = oracle.colour(g)
+    part_of = np.repeat(np.arange(len(parts)), parts)
+    assert len(set(c.tolist())) == len(parts)
+    for p_ in range(len(parts)):
+        assert len(set(c[part_of == p_].tolist())) == 1
+    first_seen = []
+    for v in _priority_order(g.n):
+        if part_of[v] not in first_seen:
+            first_seen.append(part_of[v])
+    assert [int(c[np.flatnonzero(part_of == p_)[0]]) for p_ in first_seen] == list(range(len(parts)))
+    # independent set: one colour, order = id order
+    d = oracle.orient(synth.empty(9), oracle.COLOR)
+    assert [int(x) for x in d.rank] == list(range(9))
+
+
+def test_colouring_is_lexicographically_least():
+    # Visiting vertices in priority order, first fit yields the lexicographically
+    # least proper colouring of that sequence; brute force over all colourings
+    for seed in range(6):
+        g = synth.erdos_renyi(6, 0.5, seed)
+        order = _priority_order(g.n)
+        edges = g.edges().tolist()
+        best = None
+        for cols in itertools.product(range(g.n), repeat=g.n):
+            if all(cols[a] != cols[b] for a, b in edges):
+                seq = tuple(cols[v] for v in order)
+                if best is None or seq < best:
+                    best = seq
+        c = oracle.colour(g)
+        assert tuple(int(c[v]) for v in order) == best, seed
+
+
+def test_colouring_order_invariants_and_counts():
+    for seed in range(3):
+        for g in (synth.erdos_renyi(300, 0.05, seed), synth.chung_lu(3000, 2.1, 12.0, 300.0, seed)):
+            c = oracle.colour(g)
+            e = g.edges()
+            assert np.all(c[e[:, 0]] != c[e[:, 1]]), "proper colouring"
+            deg = np.diff(g.row_ptr)
+            assert np.all(c <= deg), "first fit uses at most deg + 1 colours at a vertex"
+            d = oracle.orient(g, oracle.COLOR)
+            dag_checks(g, d)
+            assert d.degeneracy == -1
+            # (colour, id) order
+            assert np.array_equal(np.argsort(d.rank), np.lexsort((np.arange(g.n), c)))
+            dd = oracle.orient(g, oracle.DEGREE)
+            for k in (3, 4, 5):
+                assert oracle.count(d, k, False, oracle.VC) == oracle.count(dd, k, True, oracle.EC)
+
+
 # ------------------------------------------------------------- arithmetic
 
 def test_u128_boundaries():
