@@ -4,8 +4,8 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  The GPU library never loads it and shares no code with it.
 
 ``kc_oracle.c`` is a plain, single-threaded counter written from the paper
-(orientation of Sec. 3.1, the graph-orientation recursion of Fig. 2 and the
-pivoting recursion of Fig. 3), in unsigned 128-bit integer arithmetic.
+(orientation of Sec. 3.1; depth-first walks of the orientation tree of Sec. 2.2
+and the pivoting tree of Sec. 2.3), in unsigned 128-bit integer arithmetic.
 ``kc_brute.c`` is an independent brute-force enumerator for graphs of at most 64
 vertices.  This module compiles both with gcc and wraps them with ctypes over
 numpy arrays.

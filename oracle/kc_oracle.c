@@ -10,19 +10,24 @@
  *
  * What it computes
  *   c_k(G) = number of k-vertex subsets of V that are pairwise adjacent (Sec. 1
- *   problem statement), reached through the paper's two search-tree recursions:
- *     - graph orientation (Sec. 2.2, Fig. 2), vertex-rooted or edge-rooted;
- *     - pivoting (Sec. 2.3, Fig. 3) in the hybrid form of Sec. 2.3 / 2.4: the first
- *       level (vertex root) or first two levels (edge root) follow the oriented
- *       graph, every level below works on undirected adjacency.
+ *   problem statement), by walking one of the paper's two search trees from each
+ *   root, depth first with an explicit stack:
+ *     - the orientation tree (Sec. 2.2): a node is a clique with the common
+ *       out-neighbours of its vertices; vertex-rooted or edge-rooted;
+ *     - the pivoting tree (Sec. 2.3) in the hybrid form of Sec. 2.3 / 2.4: the
+ *       root level (vertex root) or two levels (edge root) follow the oriented
+ *       graph, every level below works on undirected adjacency; a node branches
+ *       only on the candidates outside its pivot's neighbourhood, and a leaf
+ *       stands for a binomial number of cliques.
  *   All intersections are merges of sorted int vectors (or binary search when one
  *   list is far shorter); there is no blocking, fusion or bit encoding here.
  *
  * Readings of the paper (each also listed in the design notes):
- *   R1  In Fig. 3, l is the number of path vertices before the branch vertex v:
- *       the vertex-rooted call starts at l = 1 (the root is a hold), the
- *       edge-rooted call at l = 2.  Then l + 1 is the path length n_v and the
- *       leaf term C(nPivots', l + 1 - k) equals Sec. 2.3's C(n_p, n_v - k).
+ *   R1  Fig. 3's level variable counts the path vertices before the branch
+ *       vertex, so a vertex root starts with one hold and an edge root with two;
+ *       a leaf whose path has n_h holds and n_p pivots then adds
+ *       C(n_p, n_h + n_p - k), which is Sec. 2.3's C(n_p, n_v - k).  The walk
+ *       keeps the holds and pivots of the path itself.
  *   R2  Pivot = argmax over u in I of |I intersect Adj(u)|; ties go to the
  *       smallest vertex id.  (Any pivot in I gives the same count.)
  *   R3  The order "<" in Fig. 3's exclusion set is vertex id order.
@@ -412,50 +417,102 @@ typedef struct {
     const binom_t* bn;
     levels_t lev;
     path_t holds, pivots;
+    int32_t* scratch;   /* d_max + 1 entries for intersections used at once */
     acc_t* acc;
 } ctx_t;
 
-/* ------------------------------------------- graph orientation (Fig. 2) */
+/* ------------------------------------------------- search-tree walks */
 
-/* Fig. 2: the l path vertices are the current clique; I holds their common
- * out-neighbours.  Each v in I extends the clique; the next level is
- * I' = I cap Adj(v).  At l + 1 == k the |I'| k-cliques are counted and the branch
- * stops.  (In count-all mode every level adds |I'| to counts[l + 1].) */
-static void go_rec(ctx_t* c, int32_t l, const int32_t* I, int32_t nI) {
-    int32_t* Ip = level_buf(&c->lev, l, 0);
-    if (!Ip) return;
-    for (int32_t i = 0; i < nI; i++) {
-        int32_t v = I[i], na;
-        const int32_t* a = outN(c->g, v, &na);
-        int32_t nIp = intersect(I, nI, a, na, Ip);
-        c->acc->nodes++;
-        if (path_set(&c->holds, l - 1, v)) { c->lev.failed = 1; return; }
-        if (c->mode == MODE_ALL) {
-            if (l + 1 <= c->acc->cap) add128(&c->acc->counts[l + 1], (u128)nIp, &c->acc->overflow);
-            if (nIp > 0) go_rec(c, l + 1, Ip, nIp);
-        } else if (l + 1 == c->k) {
-            if (c->mode == MODE_K) {
-                add128(&c->acc->total, (u128)nIp, &c->acc->overflow);
-            } else {
-                /* each of the l path vertices lies in all nIp k-cliques found
-                 * here; each vertex of I' in exactly one */
-                for (int32_t q = 0; q < l; q++)
-                    add128(&c->acc->local[c->holds.v[q]], (u128)nIp, &c->acc->overflow);
-                for (int32_t j = 0; j < nIp; j++)
-                    add128(&c->acc->local[Ip[j]], 1, &c->acc->overflow);
-            }
-        } else if (nIp > 0) {
-            go_rec(c, l + 1, Ip, nIp);
-        }
-        if (c->lev.failed) return;
+/* Both walks visit the nodes of a search tree depth first with an explicit
+ * stack of frames, one per depth.  A frame holds the node's candidate set, the
+ * vertices it branches on and how far the branching has got.  The frame at
+ * stack index i keeps its candidate set in buffer 0 of level i (the root's is
+ * the caller's) and its branch list in buffer 1; a child is always built at
+ * index i + 1, whose buffers no live frame uses.  Candidate sets stay sorted by
+ * id: each is a filtered intersection of sorted lists. */
+typedef struct {
+    const int32_t* C; int32_t nC;   /* candidate set */
+    int32_t* B; int32_t nB;         /* branch vertices, ascending */
+    int32_t next;                   /* index of the next branch in B */
+    int32_t p;                      /* pivot (pivoting walk) */
+    int32_t nh, np;                 /* holds and pivots on the path to the node */
+} frame_t;
+
+typedef struct { frame_t* f; int32_t n, cap; } fstack_t;
+static frame_t* fs_push(fstack_t* s) {
+    if (s->n == s->cap) {
+        int32_t nc = s->cap ? 2 * s->cap : 16;
+        frame_t* q = (frame_t*)realloc(s->f, (size_t)nc * sizeof(frame_t));
+        if (!q) return NULL;
+        s->f = q; s->cap = nc;
     }
+    return &s->f[s->n++];
 }
 
-/* ---------------------------------------------------- pivoting (Fig. 3) */
+/* Orientation tree (Sec. 2.2): a node is a clique Q, listed in holds[0..q), with
+ * C = the common out-neighbours of Q.  Each x in C closes the (q+1)-clique
+ * Q + x, so the node stands for |C| cliques of size q + 1; its children are
+ * Q + v with candidates C cap N+(v), for every v in C.  For a fixed k the walk
+ * stops at q = k - 1, where the |C| cliques are k-cliques; counting all sizes, it
+ * adds |C| to c_(q+1) at every node and runs until the candidate sets are empty.
+ * Every child costs one intersection: that is the node count reported. */
+static void local_add_clique_node(ctx_t* c, int32_t q, const int32_t* C, int32_t nC) {
+    /* each of the q vertices of Q is in all nC k-cliques, each x in C in one */
+    for (int32_t i = 0; i < q; i++) add128(&c->acc->local[c->holds.v[i]], (u128)nC, &c->acc->overflow);
+    for (int32_t j = 0; j < nC; j++) add128(&c->acc->local[C[j]], 1, &c->acc->overflow);
+}
 
-/* A leaf with nh holds and np pivots stands for the cliques H u P' with P' any
- * subset of the pivots (Sec. 2.3: C(n_p, n_v - k) k-cliques on a path of n_v
- * vertices). */
+/* Applies the node's contribution; returns 1 when the node has children. */
+static int orient_node(ctx_t* c, int32_t q, const int32_t* C, int32_t nC) {
+    acc_t* a = c->acc;
+    if (c->mode == MODE_ALL) {
+        if (q + 1 >= 3 && q + 1 <= a->cap) add128(&a->counts[q + 1], (u128)nC, &a->overflow);
+        return nC > 0;
+    }
+    if (q == c->k - 1) {
+        if (c->mode == MODE_K) add128(&a->total, (u128)nC, &a->overflow);
+        else local_add_clique_node(c, q, C, nC);
+        return 0;
+    }
+    return nC > 0;
+}
+
+static void orient_walk(ctx_t* c, int32_t q0, const int32_t* C0, int32_t nC0) {
+    fstack_t st = {0, 0, 0};
+    if (!orient_node(c, q0, C0, nC0)) return;
+    frame_t* f = fs_push(&st);
+    if (!f) { c->lev.failed = 1; return; }
+    *f = (frame_t){C0, nC0, NULL, 0, 0, -1, q0, 0};
+    while (st.n > 0 && !c->lev.failed) {
+        f = &st.f[st.n - 1];
+        if (f->next == f->nC) { st.n--; continue; }
+        const int32_t q = f->nh;
+        const int32_t v = f->C[f->next++];
+        if (path_set(&c->holds, q, v)) { c->lev.failed = 1; break; }
+        int32_t* C1 = level_buf(&c->lev, st.n, 0);
+        if (!C1) break;
+        int32_t na;
+        const int32_t* adj = outN(c->g, v, &na);
+        int32_t n1 = intersect(f->C, f->nC, adj, na, C1);
+        c->acc->nodes++;
+        if (orient_node(c, q + 1, C1, n1)) {
+            frame_t* g = fs_push(&st);
+            if (!g) { c->lev.failed = 1; break; }
+            *g = (frame_t){C1, n1, NULL, 0, 0, -1, q + 1, 0};
+        }
+    }
+    free(st.f);
+}
+
+/* Pivoting tree (Sec. 2.3).  A node carries holds H and pivots P (its path) and
+ * the candidate set C of common neighbours of the path, on the undirected
+ * graph.  An empty C is a leaf: it stands for the cliques H + P' with P' any
+ * subset of P, so it holds C(|P|, k - |H|) k-cliques.  Otherwise the node picks
+ * a pivot p in C (reading R2) and branches only on B = C minus N(p) (p itself
+ * included): the branch on p adds p to the pivots, any other branch v adds v to
+ * the holds.  The child on v has candidates C cap N(v) without the vertices of
+ * B that precede v (reading R3), so each clique is reached once.  For a fixed
+ * k a branch whose holds would exceed k is skipped (reading R11). */
 static void piv_leaf(ctx_t* c, int32_t nh, int32_t np) {
     acc_t* a = c->acc;
     int32_t k = c->k;
@@ -474,48 +531,55 @@ static void piv_leaf(ctx_t* c, int32_t nh, int32_t np) {
     }
 }
 
-/* Fig. 3 under reading R1: l path vertices precede the branch vertex, np of them
- * pivots; I is the candidate set (the common neighbours of the whole path). */
-static void piv_rec(ctx_t* c, int32_t l, const int32_t* I, int32_t nI, int32_t np) {
+/* Fills frame `f` (stack index idx) for a node with a non-empty candidate set:
+ * its pivot and branch list B. */
+static int piv_open(ctx_t* c, frame_t* f, int32_t idx, const int32_t* C, int32_t nC, int32_t nh, int32_t np) {
     const graph_t* g = c->g;
-    int32_t* Ip = level_buf(&c->lev, l, 0);
-    int32_t* Ipr = level_buf(&c->lev, l, 1);
-    if (!Ip || !Ipr) return;
-    /* pivot: the candidate with the most neighbours inside I (R2) */
-    int32_t p = I[0], best = -1;
-    for (int32_t i = 0; i < nI; i++) {
+    int32_t* B = level_buf(&c->lev, idx, 1);
+    if (!B) return -1;
+    /* R2: the candidate with the most neighbours inside C, smallest id on ties */
+    int32_t p = C[0], best = -1;
+    for (int32_t i = 0; i < nC; i++) {
         int32_t na;
-        const int32_t* a = undN(g, I[i], &na);
-        int32_t cnt = intersect(I, nI, a, na, Ip);
-        if (cnt > best) { best = cnt; p = I[i]; }
+        const int32_t* adj = undN(g, C[i], &na);
+        int32_t inside = intersect(C, nC, adj, na, c->scratch);
+        if (inside > best) { best = inside; p = C[i]; }
     }
-    /* I_pruned = I - Adj(p); p itself stays (no self-loops) */
-    int32_t npr = 0, pa;
+    int32_t pa, nB = 0;
     const int32_t* padj = undN(g, p, &pa);
-    for (int32_t i = 0; i < nI; i++)
-        if (!contains(padj, pa, I[i])) Ipr[npr++] = I[i];
-    int32_t nh = l - np;           /* holds before v */
-    for (int32_t i = 0; i < npr; i++) {
-        int32_t v = Ipr[i];
-        int32_t np2 = np + (v == p);
-        if (c->mode == MODE_K && (l + 1) - c->k > np2) continue;   /* stopping criterion */
+    for (int32_t i = 0; i < nC; i++)
+        if (!contains(padj, pa, C[i])) B[nB++] = C[i];
+    *f = (frame_t){C, nC, B, nB, 0, p, nh, np};
+    return 0;
+}
+
+static void piv_walk(ctx_t* c, int32_t nh0, const int32_t* C0, int32_t nC0) {
+    if (nC0 == 0) { piv_leaf(c, nh0, 0); return; }
+    fstack_t st = {0, 0, 0};
+    frame_t* f = fs_push(&st);
+    if (!f || piv_open(c, f, 0, C0, nC0, nh0, 0)) { c->lev.failed = 1; free(st.f); return; }
+    while (st.n > 0 && !c->lev.failed) {
+        f = &st.f[st.n - 1];
+        if (f->next == f->nB) { st.n--; continue; }
+        const int32_t v = f->B[f->next++];
+        const int is_pivot = v == f->p;
+        const int32_t nh = f->nh + !is_pivot, np = f->np + is_pivot;
+        if (c->mode == MODE_K && nh > c->k) continue;
+        int32_t* C1 = level_buf(&c->lev, st.n, 0);
+        if (!C1) break;
         int32_t na;
-        const int32_t* a = undN(g, v, &na);
-        int32_t n1 = intersect(I, nI, a, na, Ip);
-        /* drop the I_pruned vertices that come before v (R3: id order) */
+        const int32_t* adj = undN(c->g, v, &na);
+        int32_t n1 = intersect(f->C, f->nC, adj, na, c->scratch);
         int32_t n2 = 0;
-        for (int32_t j = 0; j < n1; j++) {
-            int32_t x = Ip[j];
-            if (x < v && contains(Ipr, npr, x)) continue;
-            Ip[n2++] = x;
-        }
+        for (int32_t j = 0; j < n1; j++)
+            if (!(c->scratch[j] < v && contains(f->B, f->nB, c->scratch[j]))) C1[n2++] = c->scratch[j];
         c->acc->nodes++;
-        int ok = (v == p) ? path_set(&c->pivots, np, v) : path_set(&c->holds, nh, v);
-        if (ok) { c->lev.failed = 1; return; }
-        if (n2 > 0) piv_rec(c, l + 1, Ip, n2, np2);
-        else piv_leaf(c, nh + (v != p), np2);
-        if (c->lev.failed) return;
+        if (is_pivot ? path_set(&c->pivots, f->np, v) : path_set(&c->holds, f->nh, v)) { c->lev.failed = 1; break; }
+        if (n2 == 0) { piv_leaf(c, nh, np); continue; }
+        frame_t* g = fs_push(&st);
+        if (!g || piv_open(c, g, st.n - 1, C1, n2, nh, np)) { c->lev.failed = 1; break; }
     }
+    free(st.f);
 }
 
 /* --------------------------------------------------------------- driver */
@@ -538,6 +602,7 @@ static int run(int32_t n, const int32_t* optr, const int32_t* ocol, const int32_
     c.lev.width = d_max + 1;
     if (pivot && binom_init(&bn, d_max + 2)) return KCO_ENOMEM;
     int32_t* I = (int32_t*)malloc((size_t)(d_max + 1) * sizeof(int32_t));
+    c.scratch = (int32_t*)malloc((size_t)(d_max + 1) * sizeof(int32_t));
     int32_t* esrc = NULL;
     if (scheme == KCO_EC) {
         esrc = (int32_t*)malloc((size_t)(m ? m : 1) * sizeof(int32_t));
@@ -545,7 +610,10 @@ static int run(int32_t n, const int32_t* optr, const int32_t* ocol, const int32_
             for (int32_t u = 0; u < n; u++)
                 for (int32_t e = optr[u]; e < optr[u + 1]; e++) esrc[e] = u;
     }
-    if (!I || (scheme == KCO_EC && !esrc)) { free(I); free(esrc); binom_free(&bn); return KCO_ENOMEM; }
+    if (!I || !c.scratch || (scheme == KCO_EC && !esrc)) {
+        free(I); free(c.scratch); free(esrc); binom_free(&bn);
+        return KCO_ENOMEM;
+    }
     int64_t nr = roots ? nroots : (scheme == KCO_VC ? n : m);
     for (int64_t r = 0; r < nr && !c.lev.failed; r++) {
         int64_t root = roots ? roots[r] : r;
@@ -566,38 +634,16 @@ static int run(int32_t n, const int32_t* optr, const int32_t* ocol, const int32_
             if (path_set(&c.holds, 0, u) || path_set(&c.holds, 1, v)) c.lev.failed = 1;
         }
         if (c.lev.failed) break;
-        if (pivot) {
-            /* hybrid (Sec. 2.3): the root level(s) are oriented, every level
-             * below pivots on the undirected adjacency; the root vertices are
-             * holds */
-            if (nI > 0) piv_rec(&c, l, I, nI, 0);
-            else piv_leaf(&c, l, 0);
-        } else if (scheme == KCO_VC) {
-            /* Fig. 2's root call: l = 2, I = N+(u) (the 2-cliques {u, v}) */
-            if (mode == MODE_ALL) { if (nI > 0) go_rec(&c, 2, I, nI); }
-            else if (k >= 3 && nI > 0) go_rec(&c, 2, I, nI);
-        } else {
-            /* edge root u->v: I = N+(u) cap N+(v) are the triangles on the edge */
-            if (mode == MODE_ALL) {
-                if (3 <= acc->cap) add128(&acc->counts[3], (u128)nI, &acc->overflow);
-                if (nI > 0) go_rec(&c, 3, I, nI);
-            } else if (k == 3) {
-                if (mode == MODE_K) {
-                    add128(&acc->total, (u128)nI, &acc->overflow);
-                } else {
-                    add128(&acc->local[c.holds.v[0]], (u128)nI, &acc->overflow);
-                    add128(&acc->local[c.holds.v[1]], (u128)nI, &acc->overflow);
-                    for (int32_t j = 0; j < nI; j++) add128(&acc->local[I[j]], 1, &acc->overflow);
-                }
-            } else if (k > 3 && nI > 0) {
-                go_rec(&c, 3, I, nI);
-            }
-        }
+        /* the root node: Q = {u} with C = N+(u), or Q = {u, v} with
+         * C = N+(u) cap N+(v); with pivoting the root vertices are holds and
+         * every level below works on the undirected graph (Sec. 2.3's hybrid) */
+        if (pivot) piv_walk(&c, l, I, nI);
+        else if (mode == MODE_ALL || k >= 3) orient_walk(&c, l, I, nI);
     }
     int failed = c.lev.failed;
     levels_free(&c.lev);
     free(c.holds.v); free(c.pivots.v);
-    free(esrc); free(I); binom_free(&bn);
+    free(esrc); free(I); free(c.scratch); binom_free(&bn);
     return failed ? KCO_ENOMEM : KCO_OK;
 }
 
