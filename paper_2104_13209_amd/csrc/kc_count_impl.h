@@ -34,6 +34,12 @@ constexpr int kLaneStealAfter = 256;   // lane walk: rounds on the current root 
 constexpr int kPivStealEvery = 64;
 constexpr int kPivStealAfter = 4096;
 constexpr int kPivStealAfterLightEC = 65536;
+// Pivot walks are latency-bound (one wavefront per tree, chains of dependent LDS
+// and global accesses), so more wavefronts may wait for handed-over frames than
+// in the lane walk: 4 per CU.  Dense-core count-all (VC / EC, ms): 1500 / 800
+// with 256 waiters in all, 1110 / 713 at 2 per CU, 930 / 665 at 4, 1240 / 775 at
+// 8, 3000 / 1390 at 16 (handoffs and queue traffic then outweigh the overlap).
+constexpr int kPivWaitersPerCU = 4;
 constexpr int kCancelEvery = 32;       // wavefront rounds (lane walk) or nodes (pivot) between cancel polls
 // count lo/hi, light/heavy stats, per width list: nodes, words, iterations,
 // expansions, busy, start, end; helper timing (3); per width list: counted

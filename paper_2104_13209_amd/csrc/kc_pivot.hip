@@ -55,6 +55,7 @@ struct PivParams {
     unsigned long long* local;               // local counts: [n], input ids
     int steal_every;                         // tree nodes between looks at the frame queue
     int steal_after;                         // nodes of the current root or frame before it may hand over
+    int max_waiters;                         // wavefronts that may wait for handed-over frames
     const int* cancel;                       // caller's cancel flag (null: none)
 };
 
@@ -243,7 +244,7 @@ __global__ void __launch_bounds__(64 * WPB) k_piv(PivParams P) {
                 if (!steal) break;
                 if (lane == 0) __hip_atomic_fetch_add(&q[Q_ROOTING], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 int stay = 1;
-                if (lane == 0 && atomicAdd(&q[Q_HUNGRY], 1) >= kMaxWaiters) {
+                if (lane == 0 && atomicAdd(&q[Q_HUNGRY], 1) >= P.max_waiters) {
                     atomicAdd(&q[Q_HUNGRY], -1);
                     stay = 0;
                 }
@@ -630,6 +631,7 @@ int pivot_launch(const PivLaunch& L, bool heavy, hipStream_t s) {
     const int mode = L.local ? 2 : (L.all ? 1 : 0);
     P.steal_every = L.steal_every > 0 ? L.steal_every : kPivStealEvery;
     P.steal_after = L.steal_after > 0 ? L.steal_after : (L.ec && !heavy ? kPivStealAfterLightEC : kPivStealAfter);
+    P.max_waiters = kPivWaitersPerCU * device_cus();
     P.cancel = L.cancel;
     if (!heavy) {
         P.s_cap = kLightCap;
