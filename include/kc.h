@@ -159,8 +159,9 @@ enum { KC_OPT_NO_HANDOFF = 1, KC_OPT_SINGLE_STREAM = 2, KC_OPT_NO_BITSETS = 4 };
  * handoff_after, handoff_every: thresholds of the handoff between wavefronts
  *   (0 = defaults: a walk may hand subtrees over after 256 wavefront rounds on
  *   its current root or subtree and looks every 16 rounds; pivot trees after
- *   4096 nodes, looking every 64).  Lower values exist for tests and
- *   measurement; counts never depend on them. */
+ *   8192 nodes, 65536 for edge roots of at most 64 candidates, looking every
+ *   64).  A value given here applies to every root list.  Lower values exist
+ *   for tests and measurement; counts never depend on them. */
 typedef struct kc_opts {
     int32_t scheme;
     int32_t width;

@@ -29,16 +29,16 @@ constexpr int kLaneStealAfter = 256;   // lane walk: rounds on the current root 
 // root or frame before it may hand over.  A consumer re-extracts the frame's
 // root, so only long trees should give work away.  Edge roots with at most 64
 // candidates (the light list) are very many short trees: their frames go only
-// after 65536 nodes (dense-core count-all 0.77 s against 2.0 s at 4096, no
-// loss on power-law graphs); vertex roots and heavy roots keep 4096.
+// after 65536 nodes; vertex roots and heavy edge roots after 8192.
 constexpr int kPivStealEvery = 64;
-constexpr int kPivStealAfter = 4096;
+constexpr int kPivStealAfter = 8192;
 constexpr int kPivStealAfterLightEC = 65536;
 // Pivot walks are latency-bound (one wavefront per tree, chains of dependent LDS
 // and global accesses), so more wavefronts may wait for handed-over frames than
-// in the lane walk: 4 per CU.  Dense-core count-all (VC / EC, ms): 1500 / 800
-// with 256 waiters in all, 1110 / 713 at 2 per CU, 930 / 665 at 4, 1240 / 775 at
-// 8, 3000 / 1390 at 16 (handoffs and queue traffic then outweigh the overlap).
+// in the lane walk: 4 per CU.  Dense-core count-all with a 4096-node first
+// handoff (VC / EC, ms): 1500 / 800 with 256 waiters in all, 1110 / 713 at 2 per
+// CU, 930 / 665 at 4, 1240 / 775 at 8, 3000 / 1390 at 16 (handoffs and queue
+// traffic then outweigh the overlap); 810 / 650 at 4 per CU with 8192.
 constexpr int kPivWaitersPerCU = 4;
 constexpr int kCancelEvery = 32;       // wavefront rounds (lane walk) or nodes (pivot) between cancel polls
 // count lo/hi, light/heavy stats, per width list: nodes, words, iterations,
