@@ -130,6 +130,20 @@ def test_long_rows_sorted(kc):
     assert np.array_equal(perm, np.argsort(oracle.orient(star, oracle.COLOR).rank, kind="stable"))
 
 
+def test_colour_order_counts_at_size(kc):
+    # the colouring DAG of the 1M-vertex power-law graph keeps hubs of up to 3779
+    # out-neighbours, so its k = 4 count runs through the wide roots; the count
+    # must equal the oracle's stored c_4 (counts do not depend on the order)
+    from conftest import load_counts
+    head, want, _ = load_counts("powerlaw_counts.txt")
+    g = synth.config_powerlaw(wmax=5656.85424949238)
+    assert (g.n, g.m) == (head["n"], head["m"])
+    d = gpu_dag(kc, g, kc.ORDER_COLOR)
+    assert d.d_max > kc.MAX_DMAX
+    for scheme in (kc.SCHEME_VC, kc.SCHEME_EC):
+        assert kc.count(d, 4, pivot=False, scheme=scheme) == want[4], scheme
+
+
 def test_config_powerlaw_orientation(kc):
     g = synth.config_powerlaw(wmax=5657.0)
     for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY, kc.ORDER_COLOR):
