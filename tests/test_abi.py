@@ -56,6 +56,13 @@ def test_host_side_argument_checks(lib):
     # a workspace that is too small is refused
     assert L.kc_count(ctypes.byref(dag), 4, 0, ctypes.byref(res), ctypes.c_void_p(1), 1, None, None) == kc.ENOMEM
     assert L.kc_orient(None, 0, None, None, 0, 1, None) == kc.EINVAL
+    # every order is accepted (a missing workspace is the next error), anything
+    # else is refused, all before any device call
+    g10 = kc._Csr(10, 20, ctypes.c_void_p(1), ctypes.c_void_p(1))
+    for order in (kc.ORDER_DEGREE, kc.ORDER_DEGENERACY, kc.ORDER_APPROX_DEGENERACY, kc.ORDER_COLOR):
+        assert L.kc_orient(ctypes.byref(g10), order, ctypes.byref(dag), None, 0, 1, None) == kc.ENOMEM, order
+    for order in (-1, 4):
+        assert L.kc_orient(ctypes.byref(g10), order, ctypes.byref(dag), None, 0, 1, None) == kc.EINVAL, order
     # kc_count_noalloc refuses a DAG whose workspace exceeds its fixed scratch
     # before touching the device
     big = kc._Dag(5_000_000, 5_000_000, 64, -1, 0, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1),
