@@ -184,8 +184,8 @@ def orient_workspace_bytes(n: int, nnz: int, order: int) -> int:
 
 def orient(g: Csr, order: int = ORDER_DEGREE, validate: bool = True, ws: torch.Tensor | None = None,
            out: Dag | None = None, stream=None) -> Dag:
-    """Orient g into a DAG by degree, degeneracy or approximate degeneracy order
-    (kc_orient)."""
+    """Orient g into a DAG by degree, degeneracy, approximate degeneracy or
+    colouring order (kc_orient)."""
     L = lib()
     dev = g.row_ptr.device
     m = g.nnz // 2
